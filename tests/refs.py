@@ -1,0 +1,145 @@
+"""Independent references used to pin the oracle (tests only).
+
+Nothing here shares code with ``oracle/``: the edit distances are textbook
+dynamic programs written out in numpy/Python, and the brute force enumerates
+walks explicitly.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def ed(a: bytes, b: bytes) -> int:
+    """Textbook global edit distance (unit costs)."""
+    a = a.upper()
+    b = b.upper()
+    prev = list(range(len(b) + 1))
+    for i in range(1, len(a) + 1):
+        cur = [i] + [0] * len(b)
+        for j in range(1, len(b) + 1):
+            cur[j] = min(prev[j] + 1, cur[j - 1] + 1, prev[j - 1] + (a[i - 1] != b[j - 1]))
+        prev = cur
+    return prev[-1]
+
+
+def semiglobal_ed_row(q: bytes, t: bytes) -> np.ndarray:
+    """Returns D[p] = ed(q, t[:p]) for every prefix length p of t (query
+    consumed globally, end free in t)."""
+    q = np.frombuffer(q.upper(), dtype=np.uint8)
+    t = np.frombuffer(t.upper(), dtype=np.uint8)
+    n, m = len(q), len(t)
+    # rows over t positions, columns over q positions: col[i] = ed(q[:i], t[:p])
+    col = np.arange(n + 1, dtype=np.int64)
+    out = np.empty(m + 1, dtype=np.int64)
+    out[0] = col[n]
+    for p in range(1, m + 1):
+        new = np.empty_like(col)
+        new[0] = p
+        sub = col[:-1] + (q != t[p - 1])
+        dele = col[1:] + 1
+        best = np.minimum(sub, dele)
+        for i in range(1, n + 1):
+            x = best[i - 1]
+            y = new[i - 1] + 1
+            new[i] = x if x < y else y
+        col = new
+        out[p] = col[n]
+    return out
+
+
+def brute_force(labels, edges, q: bytes, v_s: int):
+    """Enumerates every walk from (v_s, 0) and every end position on its last
+    vertex, with an edit-distance column carried along the spelled string;
+    a branch is abandoned once its column minimum exceeds the best distance
+    found (the column minimum never decreases as the string grows).
+    Returns (d*, end set {(v, j)})."""
+    q = (q.decode() if isinstance(q, (bytes, bytearray)) else q).upper()
+    n = len(q)
+    succ = {}
+    for a, b in edges:
+        succ.setdefault(a, []).append(b)
+    best = [n]                  # the empty prefix: all insertions
+    ends = {(v_s, 0)}           # dropped below as soon as something beats n
+    qa = list(q)
+
+    def step(col, c):
+        new = [col[0] + 1]
+        for i in range(1, n + 1):
+            new.append(min(col[i - 1] + (qa[i - 1] != c), col[i] + 1, new[i - 1] + 1))
+        return new
+
+    limit = 2 * n + 1
+
+    def dfs(v, col, depth):
+        lab = labels[v].upper()
+        for j, ch in enumerate(lab):
+            col = step(col, ch)
+            depth += 1
+            d = col[n]
+            if d < best[0]:
+                best[0] = d
+                ends.clear()        # includes the empty-prefix (v_s, 0)
+            if d == best[0]:
+                ends.add((v, j + 1))
+                # the cell before v_s's first base also holds this value when
+                # the walk can step from here into v_s (zero-cost carry)
+                if j + 1 == len(lab) and v_s in succ.get(v, []):
+                    ends.add((v_s, 0))
+            if min(col) > best[0] or depth > limit:
+                return
+        for u in succ.get(v, []):
+            dfs(u, col, depth)
+
+    dfs(v_s, list(range(n + 1)), 0)
+    return best[0], ends
+
+
+def char_split(labels, edges):
+    """Splits every vertex into a chain of one-base vertices (the paper's
+    string/char-labelled equivalence).  Returns (labels, edges, first, last,
+    cell_map) where cell_map[(v, j)] -> (v', j') for j >= 1."""
+    nl, first, last, cmap = [], [], [], {}
+    for v, s in enumerate(labels):
+        first.append(len(nl))
+        for j, ch in enumerate(s):
+            cmap[(v, j + 1)] = (len(nl), 1)
+            nl.append(ch)
+        last.append(len(nl) - 1)
+    ne = []
+    for v, s in enumerate(labels):
+        for j in range(len(s) - 1):
+            ne.append((first[v] + j, first[v] + j + 1))
+    for a, b in edges:
+        ne.append((last[a], first[b]))
+    return nl, ne, first, last, cmap
+
+
+def random_case(rng, n_vtx=5, max_label=3, p_edge=0.3, qlen=None, cyclic=True):
+    labels = ["".join("ACGT"[x] for x in rng.integers(0, 4, size=int(rng.integers(1, max_label + 1))))
+              for _ in range(n_vtx)]
+    edges = [(a, b) for a in range(n_vtx) for b in range(n_vtx)
+             if (cyclic or b > a) and rng.random() < p_edge]
+    if qlen is None:
+        qlen = int(rng.integers(0, 9))
+    q = "".join("ACGT"[x] for x in rng.integers(0, 4, size=qlen)).encode()
+    v_s = int(rng.integers(0, n_vtx))
+    return labels, edges, q, v_s
+
+
+def spell_random_walk(rng, labels, edges, v_s, max_len):
+    succ = {}
+    for a, b in edges:
+        succ.setdefault(a, []).append(b)
+    out, v = [], v_s
+    walk = [v_s]
+    total = 0
+    while True:
+        s = labels[v]
+        take = min(len(s), max_len - total)
+        out.append(s[:take])
+        total += take
+        if total >= max_len or take < len(s) or not succ.get(v):
+            break
+        v = succ[v][int(rng.integers(0, len(succ[v])))]
+        walk.append(v)
+    return "".join(out).encode(), walk

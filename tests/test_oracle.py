@@ -1,0 +1,312 @@
+"""Pins for the CPU oracle against facts that the paper and plain
+mathematics fix (no GPU needed).
+
+* brute-force walk enumeration on tiny graphs, cycles and self-loops
+  included (Def. 2.2: the optimum over all walks);
+* single-path graphs reduce to pairwise edit distance (Section 2.2: the
+  recurrence generalises the pairwise DP), end free in the target;
+* invariants: 0 <= d* <= |q|; d* = 0 for queries a walk spells; prefix
+  distances never drop and grow by at most one per base; d* <= injected edits;
+* graph transforms: splitting labels into one-base chains (the
+  string/char-labelled equivalence stated in Section 2.2), permuting vertex
+  ids and cutting one label in two leave d* and the end set unchanged;
+* the value-capped form equals the dense form;
+* Algorithms 1-3 reach the Eq. 1 optimum and end; Algorithm 4 with a huge
+  a_diff is exact and never beats the optimum otherwise; the work count
+  respects the diagonal-length bound of Section 2.4.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2206_13574_amd import synth
+from tests import refs
+
+
+# ---------------------------------------------------------------------------
+# hand-worked cases (closed forms read off Eq. 1 by hand)
+# ---------------------------------------------------------------------------
+HAND = [
+    # graph, query, v_s, d*, end(v, j)
+    ((["ACG", "T", "A", "CC"], [(0, 1), (0, 2), (1, 3), (2, 3)]), b"ACGTCC", 0, 0, (3, 2)),
+    ((["ACG", "T", "A", "CC"], [(0, 1), (0, 2), (1, 3), (2, 3)]), b"ACGACC", 0, 0, (3, 2)),
+    # G instead of T/A at the bubble: one substitution; both arms tie, the
+    # end cell (3,2) is the only end reached at cost 1
+    ((["ACG", "T", "A", "CC"], [(0, 1), (0, 2), (1, 3), (2, 3)]), b"ACGGCC", 0, 1, (3, 2)),
+    # empty query: distance 0 at (v_s, 0)
+    ((["ACG", "T"], [(0, 1)]), b"", 0, 0, (0, 0)),
+    # "TTT" against prefixes of "ACGT": the empty prefix costs 3 (insertions)
+    # and no prefix does better (ed with "ACGT" is 3 too), so d* = 3 and the
+    # start cell (0,0), which holds 3, is the smallest end cell
+    ((["ACG", "T"], [(0, 1)]), b"TTT", 0, 3, (0, 0)),
+    # self-loop: "AC" repeated; ACACAC spells 3 laps exactly.  The end of a
+    # lap carries at zero cost onto (v_s, 0), which is an end cell of the same
+    # value and sorts first
+    ((["AC"], [(0, 0)]), b"ACACAC", 0, 0, (0, 0)),
+    # self-loop with a missing base: ACAAC against ACACAC deletes one C
+    ((["AC"], [(0, 0)]), b"ACAAC", 0, 1, (0, 0)),
+    # without the loop the same query must insert past the label end
+    ((["AC"], []), b"ACAAC", 0, 3, (0, 2)),
+    # start vertex matters: same graph, start at 1
+    ((["ACG", "T", "A", "CC"], [(0, 1), (0, 2), (1, 3), (2, 3)]), b"TCC", 1, 0, (3, 2)),
+    # a query longer than every walk: the tail must be inserted
+    ((["AC", "G"], [(0, 1)]), b"ACGTT", 0, 2, (1, 1)),
+]
+
+
+@pytest.mark.parametrize("case", HAND)
+def test_hand_cases(case):
+    g, q, vs, d, end = case
+    assert O.dp_dense(g, q, vs)[:3] == (d, end[0], end[1])
+    assert O.dp_capped(g, q, vs, len(q) + 1) == (d, end[0], end[1])
+    r = O.gwf(g, q, vs)
+    assert (r["dist"], r["end_v"], r["end_j"]) == (d, end[0], end[1])
+    bd, bends = refs.brute_force(g[0], g[1], q, vs)
+    assert bd == d and end in bends and end == min(bends)
+
+
+# ---------------------------------------------------------------------------
+# brute force on random tiny graphs
+# ---------------------------------------------------------------------------
+def test_brute_force_random_tiny():
+    rng = np.random.default_rng(7)
+    n_cases = 0
+    for _ in range(400):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(1, 6)), max_label=3,
+                                                p_edge=0.35, qlen=int(rng.integers(0, 8)))
+        bd, bends = refs.brute_force(labels, edges, q, vs)
+        d, ev, ej, sweeps = O.dp_dense((labels, edges), q, vs)
+        assert d == bd, (labels, edges, q, vs)
+        assert (ev, ej) == min(bends), (labels, edges, q, vs, bends)
+        assert sweeps <= len(labels) + 1
+        n_cases += 1
+    assert n_cases == 400
+
+
+def test_brute_force_walk_spelled_queries():
+    """Queries that a walk from (v_s,0) spells have distance 0 (and brute force
+    agrees on the end)."""
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        labels, edges, _, vs = refs.random_case(rng, n_vtx=5, max_label=3, p_edge=0.35, qlen=0)
+        q, _ = refs.spell_random_walk(rng, labels, edges, vs, int(rng.integers(1, 10)))
+        d, ev, ej, _ = O.dp_dense((labels, edges), q, vs)
+        assert d == 0
+        bd, bends = refs.brute_force(labels, edges, q, vs)
+        assert bd == 0 and (ev, ej) == min(bends)
+
+
+# ---------------------------------------------------------------------------
+# single-path graphs = pairwise edit distance, end free in the target
+# ---------------------------------------------------------------------------
+def test_chain_equals_semiglobal_ed():
+    rng = np.random.default_rng(3)
+    for _ in range(60):
+        T = "".join("ACGT"[x] for x in rng.integers(0, 4, size=int(rng.integers(1, 40))))
+        cuts = sorted(set(rng.integers(1, len(T), size=int(rng.integers(0, 6))).tolist())) if len(T) > 1 else []
+        pieces = [T[a:b] for a, b in zip([0] + cuts, cuts + [len(T)])]
+        edges = [(i, i + 1) for i in range(len(pieces) - 1)]
+        if rng.random() < 0.5:   # a mutated copy of a prefix
+            q = bytearray(T[: int(rng.integers(0, len(T) + 1))].encode())
+            for _ in range(int(rng.integers(0, 4))):
+                if q and rng.random() < 0.5:
+                    q[int(rng.integers(0, len(q)))] = ord("ACGT"[int(rng.integers(0, 4))])
+                else:
+                    q.insert(int(rng.integers(0, len(q) + 1)), ord("ACGT"[int(rng.integers(0, 4))]))
+            q = bytes(q)
+        else:
+            q = "".join("ACGT"[x] for x in rng.integers(0, 4, size=int(rng.integers(0, 30)))).encode()
+        row = refs.semiglobal_ed_row(q, T.encode())
+        dstar = int(row.min())
+        p = int(np.argmin(row))           # smallest prefix length with the optimum
+        starts = np.cumsum([0] + [len(x) for x in pieces])
+        if p == 0:
+            end = (0, 0)
+        else:
+            v = int(np.searchsorted(starts, p, side="left")) - 1
+            end = (v, p - int(starts[v]))
+        got = O.dp_dense((pieces, edges), q, 0)
+        assert got[0] == dstar and got[1:3] == end, (pieces, q, row.tolist())
+        assert O.gwf((pieces, edges), q, 0)["dist"] == dstar
+
+
+def test_textbook_ed_against_library_pairwise():
+    """The oracle's pairwise routines agree with the numpy textbook DP, and the
+    banded form is exact within its band."""
+    rng = np.random.default_rng(5)
+    for _ in range(100):
+        a = "".join("ACGT"[x] for x in rng.integers(0, 4, size=int(rng.integers(0, 30)))).encode()
+        b = "".join("ACGT"[x] for x in rng.integers(0, 4, size=int(rng.integers(0, 30)))).encode()
+        e = refs.ed(a, b)
+        assert O.ed_global(a, b) == e
+        for D in (0, 1, 3, 8, 40):
+            assert O.ed_banded(a, b, D) == (e if e <= D else -1)
+
+
+# ---------------------------------------------------------------------------
+# invariants on the generated workloads
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def cfg1():
+    return synth.cfg1()
+
+
+def test_cfg1_invariants_and_capped_equals_dense(cfg1):
+    g, r = cfg1
+    for i in range(r.n):
+        q = r.read(i)
+        d, ev, ej, _ = O.dp_dense(g, q, int(r.v_start[i]))
+        assert 0 <= d <= len(q)
+        assert d <= int(r.n_edits[i])              # the generating walk aligns with that many edits
+        assert O.dp_capped(g, q, int(r.v_start[i]), int(r.n_edits[i])) == (d, ev, ej)
+        if d > 0:
+            assert O.dp_capped(g, q, int(r.v_start[i]), d - 1)[0] == -1
+        res = O.gwf(g, q, int(r.v_start[i]))
+        assert (res["dist"], res["end_v"], res["end_j"]) == (d, ev, ej)
+
+
+def test_prefix_distances_monotone(cfg1):
+    """m_i = d*(q[1..i]) never decreases and grows by at most 1 per base."""
+    g, r = cfg1
+    q = r.read(0)[:120]
+    m = [O.dp_dense(g, q[:i], int(r.v_start[0]))[0] for i in range(len(q) + 1)]
+    steps = np.diff(m)
+    assert ((steps == 0) | (steps == 1)).all()
+
+
+def test_capped_equals_dense_random():
+    rng = np.random.default_rng(21)
+    for _ in range(300):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(1, 8)), max_label=5,
+                                                p_edge=0.3, qlen=int(rng.integers(0, 25)))
+        d, ev, ej, _ = O.dp_dense((labels, edges), q, vs)
+        for D in (d, d + 1, d + 5):
+            assert O.dp_capped((labels, edges), q, vs, D) == (d, ev, ej)
+        if d > 0:
+            assert O.dp_capped((labels, edges), q, vs, d - 1)[0] == -1
+
+
+def test_gwf_equals_dense_random():
+    rng = np.random.default_rng(23)
+    for _ in range(300):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(1, 8)), max_label=5,
+                                                p_edge=0.3, qlen=int(rng.integers(0, 25)))
+        d, ev, ej, _ = O.dp_dense((labels, edges), q, vs)
+        res = O.gwf((labels, edges), q, vs)
+        assert (res["dist"], res["end_v"], res["end_j"]) == (d, ev, ej), (labels, edges, q, vs)
+
+
+def test_char_split_invariance():
+    rng = np.random.default_rng(31)
+    for _ in range(150):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(1, 6)), max_label=4,
+                                                p_edge=0.35, qlen=int(rng.integers(0, 12)))
+        bd, bends = refs.brute_force(labels, edges, q, vs)
+        nl, ne, first, last, cmap = refs.char_split(labels, edges)
+        d2, ev2, ej2, _ = O.dp_dense((nl, ne), q, first[vs])
+        assert d2 == bd
+        # the split graph's end set is the image of the original one
+        mapped = {cmap[(v, j)] if j > 0 else (first[v], 0) for v, j in bends}
+        bd2, bends2 = refs.brute_force(nl, ne, q, first[vs])
+        assert bends2 == mapped
+        assert (ev2, ej2) == min(bends2)
+
+
+def test_vertex_permutation_invariance():
+    rng = np.random.default_rng(37)
+    for _ in range(150):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(1, 7)), max_label=4,
+                                                p_edge=0.3, qlen=int(rng.integers(0, 12)))
+        bd, bends = refs.brute_force(labels, edges, q, vs)
+        perm = rng.permutation(len(labels))        # old id -> new id
+        nl = [None] * len(labels)
+        for v, s in enumerate(labels):
+            nl[perm[v]] = s
+        ne = [(int(perm[a]), int(perm[b])) for a, b in edges]
+        d2, ev2, ej2, _ = O.dp_dense((nl, ne), q, int(perm[vs]))
+        assert d2 == bd
+        assert (ev2, ej2) == min((int(perm[v]), j) for v, j in bends)
+
+
+def test_label_cut_invariance():
+    """Cutting one label in two (the pieces joined by an edge, out-edges moved
+    to the second piece) leaves d* unchanged."""
+    rng = np.random.default_rng(41)
+    for _ in range(150):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(1, 6)), max_label=6,
+                                                p_edge=0.3, qlen=int(rng.integers(0, 14)))
+        v = int(rng.integers(0, len(labels)))
+        if len(labels[v]) < 2:
+            continue
+        c = int(rng.integers(1, len(labels[v])))
+        nv = len(labels)
+        nl = labels[:v] + [labels[v][:c]] + labels[v + 1:] + [labels[v][c:]]
+        ne = []
+        for a, b in edges:
+            ne.append((nv if a == v else a, b))
+        ne.append((v, nv))
+        d = O.dp_dense((labels, edges), q, vs)[0]
+        assert O.dp_dense((nl, ne), q, vs)[0] == d
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 4 and work counts
+# ---------------------------------------------------------------------------
+def test_prune_huge_a_diff_is_exact_and_never_better(cfg1):
+    g, r = cfg1
+    for i in range(0, r.n, 5):
+        q = r.read(i)
+        vs = int(r.v_start[i])
+        ex = O.gwf(g, q, vs)
+        big = O.gwf(g, q, vs, a_diff=10 ** 8)
+        assert (big["dist"], big["end_v"], big["end_j"], big["work"]) == \
+               (ex["dist"], ex["end_v"], ex["end_j"], ex["work"])
+        for a_diff in (5, 20, 60, 200):
+            pr = O.gwf(g, q, vs, a_diff=a_diff)
+            assert pr["status"] == 0 and pr["dist"] >= ex["dist"]
+            assert pr["work"] <= ex["work"] or pr["dist"] > ex["dist"]
+
+
+def test_work_bound_section_2_4(cfg1):
+    """Each diagonal is updated at most (its length + 1) times, so the total
+    wavefront work is at most the number of diagonals times (max |v| + 1)
+    plus one per crossing."""
+    g, r = cfg1
+    lens = np.diff(g.seg_off)
+    for i in range(0, r.n, 10):
+        res = O.gwf(g, r.read(i), int(r.v_start[i]), counts_cap=4096)
+        assert sum(res["counts"]) == res["work"]
+        assert res["work"] <= res["diagonals"] * (int(lens.max()) + 1)
+
+
+def test_pairwise_wavefront_counts():
+    """On a single-vertex graph the wavefront is the pairwise one: at score s
+    it holds at most 2s+1 diagonals."""
+    rng = np.random.default_rng(2)
+    T = "".join("ACGT"[x] for x in rng.integers(0, 4, size=300))
+    q = bytearray(T[:250].encode())
+    for _ in range(12):
+        q[int(rng.integers(0, len(q)))] = ord("ACGT"[int(rng.integers(0, 4))])
+    res = O.gwf(([T], []), bytes(q), 0, counts_cap=1000)
+    for s, c in enumerate(res["counts"]):
+        assert c <= 2 * s + 1
+
+
+def test_reverse_labels_consistency(cfg1):
+    """R_{0,v_s,0} of the reverse recurrence equals d* of the forward one."""
+    import ctypes
+    g, r = cfg1
+    G = O.OGraph.of(g)
+    lib = O._load()
+    for i in range(0, r.n, 10):
+        q = np.frombuffer(r.read(i), dtype=np.uint8).copy()
+        vs = int(r.v_start[i])
+        ei = np.array([0], dtype=np.int32)
+        ev = np.array([vs], dtype=np.int32)
+        eo = np.array([0], dtype=np.int32)
+        cost = np.zeros(1, dtype=np.int32)
+        dst = np.zeros(1, dtype=np.int32)
+        rc = lib.orc_rev_labels(*G._args(), O._ptr(q), len(q), vs, O._ptr(ei), O._ptr(ev), O._ptr(eo),
+                                O._ptr(cost), 1, O._ptr(dst))
+        assert rc == 0
+        assert int(dst[0]) == O.dp_dense(g, q, vs)[0] == int(cost[0])
