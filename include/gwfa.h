@@ -1,0 +1,190 @@
+/*
+ * gwfa.h -- C ABI of the MI355X (gfx950) graph wavefront alignment library.
+ *
+ * The library aligns queries (DNA strings over A,C,G,T) to a sequence graph
+ * whose vertices carry strings and whose directed edges may form cycles
+ * (Section 2.1, Definitions 2.1 and 2.2 of Zhang, Wu, Aluru and Li, "Fast
+ * sequence to graph alignment using the graph wavefront algorithm").  For
+ * each query it returns the unit-cost edit distance of Eq. 1 (Section 2.2),
+ * the end position, and the vertex walk (Section 2.6, Algorithms 5-6).
+ *
+ * Problem form.  Extension mode: the walk starts before the first base of
+ * the start vertex, the whole query is consumed, the end is free anywhere in
+ * the graph.  The distance is the minimum of Eq. 1 over the last query row;
+ * the end (end_v, end_off) is the lexicographically smallest cell of that
+ * row holding the minimum, counting cells with end_off >= 1 plus the start
+ * cell (start vertex, 0).  end_off is the number of bases of end_v consumed.
+ * The global form with an end vertex (Definition 2.2 as printed) is reserved:
+ * opts.end_vertex >= 0 returns GWFA_ERR_UNSUPPORTED.
+ *
+ * Conventions for every call:
+ *   - every int-returning call returns GWFA_OK (0) or a negative GWFA_ERR_*;
+ *     outputs are defined only on GWFA_OK; no call aborts the process;
+ *   - "host" pointers are CPU memory, "device" pointers are HIP device memory
+ *     on the context's device; sizes are element counts unless stated;
+ *   - a context is used by one host thread at a time; a graph is immutable
+ *     after creation and may be shared by contexts on the same device.
+ */
+#ifndef GWFA_H
+#define GWFA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define GWFA_OK               0
+#define GWFA_ERR_ARG         -1   /* null pointer, negative size, bad option   */
+#define GWFA_ERR_VERTEX      -2   /* start vertex or edge endpoint out of range */
+#define GWFA_ERR_ALPHABET    -3   /* a base outside ACGT/acgt                   */
+#define GWFA_ERR_EMPTY_LABEL -4   /* a vertex with an empty string              */
+#define GWFA_ERR_NOMEM       -5   /* host or device allocation failed           */
+#define GWFA_ERR_DEVICE      -6   /* a HIP call failed (see gwfa_last_error)    */
+#define GWFA_ERR_PATH_CAP    -7   /* path buffer too small; distances valid     */
+#define GWFA_ERR_UNSUPPORTED -8   /* option not available (see each call)       */
+
+/* ---- per-query status (gwfa_result.status) ----------------------------- */
+#define GWFA_ST_OK        0
+#define GWFA_ST_MAX_SCORE 1       /* stopped at opts.max_score without an end  */
+#define GWFA_ST_ARENA     2       /* the per-query working memory overflowed at
+                                     every size tier tried                      */
+#define GWFA_ST_BAD_INPUT 3       /* start vertex out of range                  */
+
+/* ---- pruning modes (gwfa_opts.prune) ----------------------------------- */
+#define GWFA_PRUNE_NONE      0    /* exact: Algorithms 1-3                      */
+#define GWFA_PRUNE_HEURISTIC 1    /* Algorithm 4 before each expansion          */
+#define GWFA_PRUNE_LEARNED   2    /* MLP keep/drop per diagonal, fused in the
+                                     expansion (needs gwfa_mlp_load)            */
+
+typedef struct gwfa_ctx gwfa_ctx;       /* device, stream, working memory    */
+typedef struct gwfa_graph gwfa_graph;   /* packed labels + out-edge CSR      */
+
+typedef struct {
+    int32_t prune;          /* GWFA_PRUNE_*                                        */
+    int32_t a_diff;         /* heuristic: drop a diagonal when a_max - a >= a_diff,
+                               with a = query bases aligned + walk bases aligned
+                               (Algorithm 4); must be >= 1 when prune = 1          */
+    float keep_threshold;   /* learned: keep when the MLP logit >= keep_threshold   */
+    int32_t traceback;      /* 1: fill walks (Algorithms 5-6); 0: distances only     */
+    int32_t max_score;      /* -1: unbounded; else stop a query past this score     */
+    int32_t end_vertex;     /* -1: extension mode; >= 0 reserved (UNSUPPORTED)      */
+    int32_t mlp_gate;       /* learned: run the MLP only when |F_s| >= mlp_gate     */
+    int32_t mlp_period;     /* learned: run the MLP every mlp_period scores (>= 1)  */
+} gwfa_opts;
+
+typedef struct {
+    int32_t dist;           /* edit distance d*, -1 unless status == GWFA_ST_OK   */
+    int32_t end_v;          /* end vertex                                          */
+    int32_t end_off;        /* bases of end_v consumed, 1..|end_v| (0 only for the
+                               start vertex)                                       */
+    int32_t status;         /* GWFA_ST_*                                           */
+    int64_t path_off;       /* first vertex of the walk in path_buf, -1 if none    */
+    int32_t path_len;       /* vertices in the walk (start ... end_v)              */
+    int32_t n_scores;       /* scores run (dist + 1 on success)                    */
+    int64_t work;           /* sum over scores s of |F_s| (entries after extension) */
+} gwfa_result;              /* 40 bytes */
+
+/* Default options: exact, traceback on, unbounded, extension mode. */
+void gwfa_opts_default(gwfa_opts *opts);
+
+/* Error text for a GWFA_ERR_* code (static storage). */
+const char *gwfa_strerror(int code);
+
+/* Last device-side error message kept in the context ("" if none). */
+const char *gwfa_last_error(const gwfa_ctx *ctx);
+
+/* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t on
+ * that device or NULL for a library-owned stream; the library never destroys a
+ * caller's stream.  Working memory is allocated on the first alignment call. */
+int gwfa_ctx_create(int device, void *hip_stream, gwfa_ctx **out);
+void gwfa_ctx_destroy(gwfa_ctx *ctx);
+
+/* Working-memory / launch configuration (used by the autotuner).
+ *   lanes_per_query: 64, 128 or 256 threads cooperate on one query;
+ *   n_groups: persistent workgroups (0 = one per compute unit x 4);
+ *   dir_log2_max: log2 of the largest per-query diagonal-page directory
+ *                 (each page holds 32 diagonals of one vertex; 10..22);
+ *   list_cap: capacity of each per-query wavefront list (entries);
+ *   dir_factor: initial directory slots per 32 query bases (power of two).
+ * Returns GWFA_ERR_ARG on a value out of range.  Frees working memory, which
+ * is reallocated on the next call. */
+int gwfa_ctx_config(gwfa_ctx *ctx, int32_t lanes_per_query, int32_t n_groups,
+                    int32_t dir_log2_max, int32_t list_cap, int32_t dir_factor);
+
+/* Builds a graph (Definition 2.1).  Host inputs, copied; the caller may free
+ * them on return.
+ *   seq      ASCII labels of all vertices concatenated (A,C,G,T, any case);
+ *   seq_off  n_vtx+1 offsets into seq, non-decreasing; |v| = seq_off[v+1] -
+ *            seq_off[v] must be >= 1 (GWFA_ERR_EMPTY_LABEL);
+ *   edge_src, edge_dst  n_edge directed edges (u, v), 0 <= u, v < n_vtx
+ *            (GWFA_ERR_VERTEX); self-loops and repeated edges are allowed.
+ * The labels are packed 2 bits per base (A0 C1 G2 T3, first base in the most
+ * significant bits, 32 bases per 64-bit word) and the edges are stored as an
+ * out-edge CSR in device memory. */
+int gwfa_graph_create(gwfa_ctx *ctx, int32_t n_vtx, const uint8_t *seq, const int64_t *seq_off,
+                      int64_t n_edge, const int32_t *edge_src, const int32_t *edge_dst,
+                      gwfa_graph **out);
+void gwfa_graph_destroy(gwfa_graph *g);
+
+/* Packs n_bases ASCII bases (device) into 2-bit words (device, at least
+ * gwfa_packed_words(n_bases) words: the 2-word zero tail is written too) on
+ * `hip_stream` (NULL = context stream).  A base outside ACGT/acgt sets
+ * *d_err (device int32, the caller clears it first) to GWFA_ERR_ALPHABET;
+ * such bases are packed as A.  Asynchronous. */
+int gwfa_pack_dev(gwfa_ctx *ctx, const uint8_t *d_ascii, int64_t n_bases, uint64_t *d_packed,
+                  int32_t *d_err, void *hip_stream);
+int64_t gwfa_packed_words(int64_t n_bases);
+
+/* Aligns n_reads queries (host buffers).
+ *   reads     ASCII queries concatenated; read_off n_reads+1 offsets (bases);
+ *   v_start   start vertex per query;
+ *   res       n_reads results (host, caller-owned);
+ *   path_buf  host buffer of path_cap vertex ids for the walks (may be NULL
+ *             when opts->traceback == 0); *path_needed receives the number of
+ *             ids the walks need (may be NULL).
+ * Validates everything (ALPHABET, VERTEX, ARG) before any device work.
+ * Returns GWFA_ERR_PATH_CAP when the walks do not fit; distances and ends are
+ * then valid and the walks' path_off are -1.  Synchronous. */
+int gwfa_align_batch(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, const uint8_t *reads,
+                     const int64_t *read_off, const int32_t *v_start, const gwfa_opts *opts,
+                     gwfa_result *res, int32_t *path_buf, int64_t path_cap, int64_t *path_needed);
+
+/* The same on device-resident inputs (the form the Python binding uses).
+ *   d_packed   packed queries (gwfa_pack_dev layout, 2-word zero tail);
+ *   d_read_off n_reads+1 int64 base offsets; d_v_start n_reads int32;
+ *   d_order    optional int32 permutation of 0..n_reads-1 giving the order in
+ *              which queries are taken from the work queue (NULL = 0,1,2,...;
+ *              longest first balances the load best);
+ *   d_res      n_reads gwfa_result; d_path_buf path_cap int32 (may be NULL);
+ *   d_path_used  device int64: receives the ids the walks need.
+ * Start vertices are checked on the device (status GWFA_ST_BAD_INPUT).
+ * Runs on `hip_stream` (NULL = context stream).  When some query overflows its
+ * working memory the library synchronises the stream and re-runs those
+ * queries with larger memory before returning; otherwise the call is
+ * asynchronous.  Returns GWFA_ERR_PATH_CAP only from gwfa_align_batch (here
+ * the caller compares *d_path_used with path_cap). */
+int gwfa_align_batch_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, const uint64_t *d_packed,
+                         const int64_t *d_read_off, const int32_t *d_v_start, const int32_t *d_order,
+                         const gwfa_opts *opts, gwfa_result *d_res, int32_t *d_path_buf, int64_t path_cap,
+                         int64_t *d_path_used, void *hip_stream);
+
+/* Loads the pruning network used with GWFA_PRUNE_LEARNED: 8 features ->
+ * 64 ReLU -> 64 ReLU -> 1 logit, bfloat16 values in the order W1[64][8],
+ * b1[64], W2[64][64], b2[64], W3[64], b3 (4801 values), plus 8 float
+ * feature scales (features are multiplied by them after log1p).
+ * Host pointers, copied. */
+int gwfa_mlp_load(gwfa_ctx *ctx, const uint16_t *bf16_weights, int64_t n, const float *feat_scale);
+
+/* Kernel-level counters accumulated since the last reset (device totals over
+ * every query): [0] wavefront entries (sum |F_s|), [1] crossings admitted,
+ * [2] pages created, [3] 32-base compare chunks in the extension,
+ * [4] expansion candidates admitted, [5] queries re-run for memory,
+ * [6] MLP evaluations, [7] entries dropped by pruning. */
+int gwfa_stats(gwfa_ctx *ctx, int64_t *out8, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GWFA_H */

@@ -1,0 +1,504 @@
+// gwfa_host.cpp -- host side of the C ABI declared in include/gwfa.h:
+// contexts, graphs, working memory (per-workgroup HBM arenas in size tiers),
+// validation, launches and the overflow re-run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "gwfa.h"
+#include "gwfa_internal.h"
+
+#ifndef GWFA_HAVE_LEARNED
+#define GWFA_HAVE_LEARNED 0
+#endif
+
+namespace {
+
+constexpr int N_TIERS = 3;
+
+struct Tier {
+    int32_t dir_log2_max = 16;
+    int32_t list_cap = 1 << 15;
+    int32_t cand_cap = 1 << 16;
+    int32_t groups = 0;
+    char* arena = nullptr;
+    int64_t stride = 0;
+    int64_t o_dir = 0, o_pages = 0, o_mkey = 0, o_mval = 0, o_tv = 0, o_tt = 0, o_lists = 0, o_cand = 0;
+};
+
+int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+void layout(Tier& t) {
+    const int64_t C = (int64_t)1 << t.dir_log2_max;
+    int64_t o = 0;
+    t.o_dir = o;   o = align_up(o + C * 8, 512);
+    t.o_pages = o; o = align_up(o + C * 512, 512);
+    t.o_mkey = o;  o = align_up(o + C * 8, 256);
+    t.o_mval = o;  o = align_up(o + C * 4, 256);
+    t.o_tv = o;    o = align_up(o + (C / 2) * 4, 256);
+    t.o_tt = o;    o = align_up(o + (C / 2) * 4, 256);
+    t.o_lists = o; o = align_up(o + (int64_t)2 * 6 * t.list_cap * 4, 256);
+    t.o_cand = o;  o = align_up(o + (int64_t)5 * t.cand_cap * 4, 4096);
+    t.stride = o;
+}
+
+}  // namespace
+
+struct gwfa_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int32_t lanes = 256;
+    int32_t groups = 0;
+    int32_t dir_factor = 16;
+    Tier tier[N_TIERS];
+    int32_t* d_queue = nullptr;
+    unsigned long long* d_cursor = nullptr;
+    int32_t* d_retry_count = nullptr;
+    unsigned long long* d_stats = nullptr;
+    int32_t* d_retry[2] = {nullptr, nullptr};
+    int64_t retry_cap = 0;
+    int64_t rerun_total = 0;
+    uint16_t* d_mlp = nullptr;
+    float* d_mlp_scale = nullptr;
+    bool mlp_loaded = false;
+    int n_cu = 256;
+    std::string err;
+};
+
+struct gwfa_graph {
+    gwfa_ctx* ctx = nullptr;
+    int32_t n_vtx = 0;
+    int64_t n_edge = 0;
+    int64_t bases = 0;
+    unsigned long long* d_seg = nullptr;
+    int64_t* d_seg_off = nullptr;
+    int32_t* d_out_off = nullptr;
+    int32_t* d_out_dst = nullptr;
+};
+
+namespace {
+
+int dev_fail(gwfa_ctx* ctx, hipError_t e, const char* what) {
+    if (ctx) {
+        ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return GWFA_ERR_DEVICE;
+}
+
+#define HIPCHK(ctx, call)                                              \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return dev_fail((ctx), e_, #call);       \
+    } while (0)
+
+inline bool is_acgt(uint8_t c) {
+    const uint8_t u = c & 0xdf;
+    return u == 'A' || u == 'C' || u == 'G' || u == 'T';
+}
+
+void free_tier(Tier& t) {
+    if (t.arena) (void)hipFree(t.arena);
+    t.arena = nullptr;
+}
+
+int ensure_tier(gwfa_ctx* ctx, int ti) {
+    Tier& t = ctx->tier[ti];
+    if (t.arena) return GWFA_OK;
+    layout(t);
+    size_t bytes = (size_t)t.stride * (size_t)t.groups;
+    hipError_t e = hipMalloc((void**)&t.arena, bytes);
+    if (e != hipSuccess) {
+        t.arena = nullptr;
+        ctx->err = "arena allocation of " + std::to_string(bytes) + " bytes failed";
+        return GWFA_ERR_NOMEM;
+    }
+    return GWFA_OK;
+}
+
+void set_tiers(gwfa_ctx* ctx, int32_t dir_log2_max, int32_t list_cap) {
+    int groups = ctx->groups > 0 ? ctx->groups : ctx->n_cu * 4;
+    for (int i = 0; i < N_TIERS; ++i) {
+        free_tier(ctx->tier[i]);
+        Tier& t = ctx->tier[i];
+        t.dir_log2_max = std::min(dir_log2_max + 2 * i, 24);
+        t.list_cap = (int32_t)std::min<int64_t>((int64_t)list_cap << (2 * i), (int64_t)1 << 26);
+        t.cand_cap = (int32_t)std::min<int64_t>((int64_t)t.list_cap * 2, (int64_t)1 << 27);
+        t.groups = std::max(4, groups >> (3 * i));
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void gwfa_opts_default(gwfa_opts* o) {
+    if (!o) return;
+    o->prune = GWFA_PRUNE_NONE;
+    o->a_diff = 0;
+    o->keep_threshold = 0.0f;
+    o->traceback = 1;
+    o->max_score = -1;
+    o->end_vertex = -1;
+    o->mlp_gate = 0;
+    o->mlp_period = 1;
+}
+
+const char* gwfa_strerror(int code) {
+    switch (code) {
+    case GWFA_OK: return "ok";
+    case GWFA_ERR_ARG: return "invalid argument";
+    case GWFA_ERR_VERTEX: return "vertex id out of range";
+    case GWFA_ERR_ALPHABET: return "base outside A,C,G,T";
+    case GWFA_ERR_EMPTY_LABEL: return "vertex with an empty label";
+    case GWFA_ERR_NOMEM: return "out of memory";
+    case GWFA_ERR_DEVICE: return "HIP runtime error";
+    case GWFA_ERR_PATH_CAP: return "path buffer too small";
+    case GWFA_ERR_UNSUPPORTED: return "unsupported option";
+    default: return "unknown error";
+    }
+}
+
+const char* gwfa_last_error(const gwfa_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int gwfa_ctx_create(int device, void* hip_stream, gwfa_ctx** out) {
+    if (!out || device < 0) return GWFA_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return GWFA_ERR_DEVICE;
+    gwfa_ctx* c = new (std::nothrow) gwfa_ctx();
+    if (!c) return GWFA_ERR_NOMEM;
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) { delete c; return GWFA_ERR_DEVICE; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->n_cu = prop.multiProcessorCount;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return GWFA_ERR_DEVICE; }
+        c->own_stream = true;
+    }
+    bool ok = hipMalloc((void**)&c->d_queue, sizeof(int32_t)) == hipSuccess &&
+              hipMalloc((void**)&c->d_cursor, sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc((void**)&c->d_retry_count, sizeof(int32_t)) == hipSuccess &&
+              hipMalloc((void**)&c->d_stats, 8 * sizeof(unsigned long long)) == hipSuccess;
+    if (ok) ok = hipMemset(c->d_stats, 0, 8 * sizeof(unsigned long long)) == hipSuccess;
+    if (!ok) { gwfa_ctx_destroy(c); return GWFA_ERR_NOMEM; }
+    set_tiers(c, 16, 1 << 15);
+    *out = c;
+    return GWFA_OK;
+}
+
+void gwfa_ctx_destroy(gwfa_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& t : c->tier) free_tier(t);
+    if (c->d_queue) (void)hipFree(c->d_queue);
+    if (c->d_cursor) (void)hipFree(c->d_cursor);
+    if (c->d_retry_count) (void)hipFree(c->d_retry_count);
+    if (c->d_stats) (void)hipFree(c->d_stats);
+    for (auto p : c->d_retry) if (p) (void)hipFree(p);
+    if (c->d_mlp) (void)hipFree(c->d_mlp);
+    if (c->d_mlp_scale) (void)hipFree(c->d_mlp_scale);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int gwfa_ctx_config(gwfa_ctx* c, int32_t lanes, int32_t n_groups, int32_t dir_log2_max, int32_t list_cap,
+                    int32_t dir_factor) {
+    if (!c) return GWFA_ERR_ARG;
+    if (lanes != 64 && lanes != 128 && lanes != 256) return GWFA_ERR_ARG;
+    if (n_groups < 0 || n_groups > (1 << 20)) return GWFA_ERR_ARG;
+    if (dir_log2_max < 10 || dir_log2_max > 22) return GWFA_ERR_ARG;
+    if (list_cap < 1024 || list_cap > (1 << 24)) return GWFA_ERR_ARG;
+    if (dir_factor < 1 || dir_factor > 4096 || (dir_factor & (dir_factor - 1))) return GWFA_ERR_ARG;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    c->lanes = lanes;
+    c->groups = n_groups;
+    c->dir_factor = dir_factor;
+    set_tiers(c, dir_log2_max, list_cap);
+    return GWFA_OK;
+}
+
+int64_t gwfa_packed_words(int64_t n_bases) { return n_bases < 0 ? 0 : (n_bases + 31) / 32 + 2; }
+
+int gwfa_graph_create(gwfa_ctx* ctx, int32_t n_vtx, const uint8_t* seq, const int64_t* seq_off, int64_t n_edge,
+                      const int32_t* edge_src, const int32_t* edge_dst, gwfa_graph** out) {
+    if (!ctx || !out || n_vtx <= 0 || !seq_off || n_edge < 0) return GWFA_ERR_ARG;
+    if (n_edge > 0 && (!edge_src || !edge_dst)) return GWFA_ERR_ARG;
+    *out = nullptr;
+    if (seq_off[0] != 0) return GWFA_ERR_ARG;
+    for (int32_t v = 0; v < n_vtx; ++v) {
+        if (seq_off[v + 1] < seq_off[v]) return GWFA_ERR_ARG;
+        if (seq_off[v + 1] == seq_off[v]) return GWFA_ERR_EMPTY_LABEL;
+    }
+    const int64_t bases = seq_off[n_vtx];
+    if (bases > 0 && !seq) return GWFA_ERR_ARG;
+    if (bases >= ((int64_t)1 << 40)) return GWFA_ERR_ARG;
+    for (int64_t i = 0; i < bases; ++i)
+        if (!is_acgt(seq[i])) return GWFA_ERR_ALPHABET;
+    for (int32_t v = 0; v < n_vtx; ++v)
+        if (seq_off[v + 1] - seq_off[v] > (int64_t)1 << 30) return GWFA_ERR_ARG;
+    for (int64_t e = 0; e < n_edge; ++e)
+        if (edge_src[e] < 0 || edge_src[e] >= n_vtx || edge_dst[e] < 0 || edge_dst[e] >= n_vtx) return GWFA_ERR_VERTEX;
+    if (n_edge > INT32_MAX) return GWFA_ERR_ARG;
+
+    // out-edge CSR (edges of a vertex keep their input order)
+    std::vector<int32_t> off(n_vtx + 1, 0), dst((size_t)std::max<int64_t>(n_edge, 1));
+    for (int64_t e = 0; e < n_edge; ++e) off[edge_src[e] + 1]++;
+    for (int32_t v = 0; v < n_vtx; ++v) off[v + 1] += off[v];
+    {
+        std::vector<int32_t> fill(off.begin(), off.end() - 1);
+        for (int64_t e = 0; e < n_edge; ++e) dst[fill[edge_src[e]]++] = edge_dst[e];
+    }
+    gwfa_graph* g = new (std::nothrow) gwfa_graph();
+    if (!g) return GWFA_ERR_NOMEM;
+    g->ctx = ctx; g->n_vtx = n_vtx; g->n_edge = n_edge; g->bases = bases;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int64_t words = gwfa_packed_words(bases);
+    uint8_t* d_ascii = nullptr;
+    int32_t* d_err = nullptr;
+    bool ok = hipMalloc((void**)&g->d_seg, words * 8) == hipSuccess &&
+              hipMalloc((void**)&g->d_seg_off, (size_t)(n_vtx + 1) * 8) == hipSuccess &&
+              hipMalloc((void**)&g->d_out_off, (size_t)(n_vtx + 1) * 4) == hipSuccess &&
+              hipMalloc((void**)&g->d_out_dst, dst.size() * 4) == hipSuccess &&
+              hipMalloc((void**)&d_ascii, (size_t)std::max<int64_t>(bases, 1)) == hipSuccess &&
+              hipMalloc((void**)&d_err, 4) == hipSuccess;
+    if (!ok) {
+        if (d_ascii) (void)hipFree(d_ascii);
+        if (d_err) (void)hipFree(d_err);
+        gwfa_graph_destroy(g);
+        return GWFA_ERR_NOMEM;
+    }
+    hipStream_t st = ctx->stream;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(d_ascii, seq, (size_t)bases, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(d_err, 0, 4, st);
+    if (e == hipSuccess) e = gwfa_launch_pack(d_ascii, bases, g->d_seg, words, d_err, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->d_seg_off, seq_off, (size_t)(n_vtx + 1) * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->d_out_off, off.data(), (size_t)(n_vtx + 1) * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->d_out_dst, dst.data(), dst.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d_ascii);
+    (void)hipFree(d_err);
+    if (e != hipSuccess) {
+        gwfa_graph_destroy(g);
+        return dev_fail(ctx, e, "graph upload");
+    }
+    *out = g;
+    return GWFA_OK;
+}
+
+void gwfa_graph_destroy(gwfa_graph* g) {
+    if (!g) return;
+    if (g->ctx) (void)hipSetDevice(g->ctx->device);
+    if (g->d_seg) (void)hipFree(g->d_seg);
+    if (g->d_seg_off) (void)hipFree(g->d_seg_off);
+    if (g->d_out_off) (void)hipFree(g->d_out_off);
+    if (g->d_out_dst) (void)hipFree(g->d_out_dst);
+    delete g;
+}
+
+int gwfa_pack_dev(gwfa_ctx* ctx, const uint8_t* d_ascii, int64_t n_bases, uint64_t* d_packed, int32_t* d_err,
+                  void* hip_stream) {
+    if (!ctx || n_bases < 0 || !d_packed || (n_bases > 0 && !d_ascii)) return GWFA_ERR_ARG;
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, gwfa_launch_pack(d_ascii, n_bases, (unsigned long long*)d_packed, gwfa_packed_words(n_bases), d_err, st));
+    return GWFA_OK;
+}
+
+static int check_opts(const gwfa_ctx* ctx, const gwfa_opts* o) {
+    if (!o) return GWFA_ERR_ARG;
+    if (o->end_vertex >= 0) return GWFA_ERR_UNSUPPORTED;
+    if (o->prune < 0 || o->prune > 2) return GWFA_ERR_ARG;
+    if (o->prune == GWFA_PRUNE_HEURISTIC && o->a_diff < 1) return GWFA_ERR_ARG;
+    if (o->prune == GWFA_PRUNE_LEARNED) {
+        if (!ctx->mlp_loaded || !GWFA_HAVE_LEARNED) return GWFA_ERR_UNSUPPORTED;
+        if (o->mlp_period < 1 || o->mlp_gate < 0) return GWFA_ERR_ARG;
+    }
+    if (o->max_score < -1) return GWFA_ERR_ARG;
+    if (o->traceback != 0 && o->traceback != 1) return GWFA_ERR_ARG;
+    return GWFA_OK;
+}
+
+int gwfa_align_batch_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
+                         const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_order,
+                         const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
+                         int64_t* d_path_used, void* hip_stream) {
+    if (!ctx || !g || n_reads < 0 || path_cap < 0) return GWFA_ERR_ARG;
+    if (g->ctx && g->ctx->device != ctx->device) return GWFA_ERR_ARG;
+    int rc = check_opts(ctx, opts);
+    if (rc) return rc;
+    if (n_reads == 0) return GWFA_OK;
+    if (!d_packed || !d_read_off || !d_v_start || !d_res) return GWFA_ERR_ARG;
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+
+    if (ctx->retry_cap < n_reads) {
+        for (auto& p : ctx->d_retry) { if (p) (void)hipFree(p); p = nullptr; }
+        ctx->retry_cap = 0;
+        for (auto& p : ctx->d_retry)
+            if (hipMalloc((void**)&p, (size_t)n_reads * 4) != hipSuccess) return GWFA_ERR_NOMEM;
+        ctx->retry_cap = n_reads;
+    }
+    KArgs A;
+    memset(&A, 0, sizeof(A));
+    A.seg = g->d_seg; A.seg_off = g->d_seg_off; A.out_off = g->d_out_off; A.out_dst = g->d_out_dst; A.n_vtx = g->n_vtx;
+    A.rd = (const unsigned long long*)d_packed; A.rd_off = d_read_off; A.v_start = d_v_start;
+    A.res = d_res; A.path_buf = d_path_buf; A.path_cap = d_path_buf ? path_cap : 0;
+    A.path_cursor = d_path_used ? (unsigned long long*)d_path_used : ctx->d_cursor;
+    A.queue = ctx->d_queue; A.stats = ctx->d_stats;
+    A.retry_count = ctx->d_retry_count;
+    A.prune = opts->prune; A.a_diff = opts->a_diff; A.traceback = opts->traceback; A.max_score = opts->max_score;
+    A.keep_threshold = opts->keep_threshold; A.mlp_gate = opts->mlp_gate; A.mlp_period = opts->mlp_period;
+    A.mlp_w = ctx->d_mlp; A.mlp_scale = ctx->d_mlp_scale;
+    A.dir_factor = ctx->dir_factor;
+
+    const int32_t* order = d_order;
+    int32_t n = n_reads;
+    HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, A.path_cursor, ctx->d_retry_count, st));
+    for (int ti = 0; ti < N_TIERS; ++ti) {
+        if ((rc = ensure_tier(ctx, ti))) return rc;
+        const Tier& t = ctx->tier[ti];
+        A.order = order; A.n_reads = n;
+        A.retry = (ti + 1 < N_TIERS) ? ctx->d_retry[ti & 1] : nullptr;
+        A.arena = t.arena; A.arena_stride = t.stride;
+        A.dir_log2_max = t.dir_log2_max; A.list_cap = t.list_cap; A.cand_cap = t.cand_cap;
+        A.o_dir = t.o_dir; A.o_pages = t.o_pages; A.o_mkey = t.o_mkey; A.o_mval = t.o_mval;
+        A.o_tv = t.o_tv; A.o_tt = t.o_tt; A.o_lists = t.o_lists; A.o_cand = t.o_cand;
+        const int groups = std::min<int64_t>(t.groups, n);
+        HIPCHK(ctx, gwfa_launch_align(A, ctx->lanes, groups, st));
+        if (ti + 1 == N_TIERS) break;
+        int32_t h_retry = 0;
+        HIPCHK(ctx, hipMemcpyAsync(&h_retry, ctx->d_retry_count, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        if (h_retry <= 0) break;
+        ctx->rerun_total += h_retry;
+        order = ctx->d_retry[ti & 1];
+        n = h_retry;
+        // reset the queue and the retry counter, keep the path cursor
+        HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, nullptr, ctx->d_retry_count, st));
+    }
+    return GWFA_OK;
+}
+
+int gwfa_align_batch(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint8_t* reads,
+                     const int64_t* read_off, const int32_t* v_start, const gwfa_opts* opts, gwfa_result* res,
+                     int32_t* path_buf, int64_t path_cap, int64_t* path_needed) {
+    if (!ctx || !g || n_reads < 0 || path_cap < 0) return GWFA_ERR_ARG;
+    int rc = check_opts(ctx, opts);
+    if (rc) return rc;
+    if (path_needed) *path_needed = 0;
+    if (n_reads == 0) return GWFA_OK;
+    if (!read_off || !v_start || !res) return GWFA_ERR_ARG;
+    if (read_off[0] != 0) return GWFA_ERR_ARG;
+    for (int32_t r = 0; r < n_reads; ++r) {
+        if (read_off[r + 1] < read_off[r]) return GWFA_ERR_ARG;
+        if (read_off[r + 1] - read_off[r] > ((int64_t)1 << 30)) return GWFA_ERR_ARG;
+        if (v_start[r] < 0 || v_start[r] >= g->n_vtx) return GWFA_ERR_VERTEX;
+    }
+    const int64_t bases = read_off[n_reads];
+    if (bases > 0 && !reads) return GWFA_ERR_ARG;
+    for (int64_t i = 0; i < bases; ++i)
+        if (!is_acgt(reads[i])) return GWFA_ERR_ALPHABET;
+    // longest queries first
+    std::vector<int32_t> order(n_reads);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return read_off[a + 1] - read_off[a] > read_off[b + 1] - read_off[b];
+    });
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int64_t words = gwfa_packed_words(bases);
+    uint8_t* d_ascii = nullptr;
+    unsigned long long* d_packed = nullptr;
+    int64_t* d_off = nullptr;
+    int32_t *d_vs = nullptr, *d_order = nullptr, *d_err = nullptr, *d_path = nullptr;
+    gwfa_result* d_res = nullptr;
+    int64_t* d_used = nullptr;
+    const bool want_path = opts->traceback && path_buf && path_cap > 0;
+    bool ok = hipMalloc((void**)&d_ascii, (size_t)std::max<int64_t>(bases, 1)) == hipSuccess &&
+              hipMalloc((void**)&d_packed, (size_t)words * 8) == hipSuccess &&
+              hipMalloc((void**)&d_off, (size_t)(n_reads + 1) * 8) == hipSuccess &&
+              hipMalloc((void**)&d_vs, (size_t)n_reads * 4) == hipSuccess &&
+              hipMalloc((void**)&d_order, (size_t)n_reads * 4) == hipSuccess &&
+              hipMalloc((void**)&d_err, 4) == hipSuccess &&
+              hipMalloc((void**)&d_res, (size_t)n_reads * sizeof(gwfa_result)) == hipSuccess &&
+              hipMalloc((void**)&d_used, 8) == hipSuccess &&
+              (!want_path || hipMalloc((void**)&d_path, (size_t)path_cap * 4) == hipSuccess);
+    int out_rc = ok ? GWFA_OK : GWFA_ERR_NOMEM;
+    hipError_t e = hipSuccess;
+    if (ok) {
+        if (e == hipSuccess) e = hipMemcpyAsync(d_ascii, reads, (size_t)bases, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_off, read_off, (size_t)(n_reads + 1) * 8, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_vs, v_start, (size_t)n_reads * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), (size_t)n_reads * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemsetAsync(d_err, 0, 4, st);
+        if (e == hipSuccess) e = gwfa_launch_pack(d_ascii, bases, d_packed, words, d_err, st);
+        if (e != hipSuccess) out_rc = dev_fail(ctx, e, "query upload");
+    }
+    if (out_rc == GWFA_OK)
+        out_rc = gwfa_align_batch_dev(ctx, g, n_reads, (const uint64_t*)d_packed, d_off, d_vs, d_order, opts, d_res,
+                                      want_path ? d_path : nullptr, want_path ? path_cap : 0, d_used, st);
+    if (out_rc == GWFA_OK) {
+        int64_t used = 0;
+        e = hipMemcpyAsync(res, d_res, (size_t)n_reads * sizeof(gwfa_result), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&used, d_used, 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess && want_path && used > 0)
+            e = hipMemcpy(path_buf, d_path, (size_t)std::min(used, path_cap) * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) out_rc = dev_fail(ctx, e, "result download");
+        if (out_rc == GWFA_OK) {
+            if (path_needed) *path_needed = opts->traceback ? used : 0;
+            if (opts->traceback && used > (want_path ? path_cap : 0)) out_rc = GWFA_ERR_PATH_CAP;
+        }
+    }
+    if (d_ascii) (void)hipFree(d_ascii);
+    if (d_packed) (void)hipFree(d_packed);
+    if (d_off) (void)hipFree(d_off);
+    if (d_vs) (void)hipFree(d_vs);
+    if (d_order) (void)hipFree(d_order);
+    if (d_err) (void)hipFree(d_err);
+    if (d_res) (void)hipFree(d_res);
+    if (d_used) (void)hipFree(d_used);
+    if (d_path) (void)hipFree(d_path);
+    return out_rc;
+}
+
+int gwfa_mlp_load(gwfa_ctx* ctx, const uint16_t* w, int64_t n, const float* scale) {
+    if (!ctx || !w || !scale || n != 4801) return GWFA_ERR_ARG;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if (!ctx->d_mlp) HIPCHK(ctx, hipMalloc((void**)&ctx->d_mlp, 4808 * 2));
+    if (!ctx->d_mlp_scale) HIPCHK(ctx, hipMalloc((void**)&ctx->d_mlp_scale, 8 * 4));
+    HIPCHK(ctx, hipMemcpy(ctx->d_mlp, w, (size_t)n * 2, hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(ctx->d_mlp_scale, scale, 8 * 4, hipMemcpyHostToDevice));
+    ctx->mlp_loaded = true;
+    return GWFA_OK;
+}
+
+int gwfa_stats(gwfa_ctx* ctx, int64_t* out8, int32_t reset) {
+    if (!ctx || !out8) return GWFA_ERR_ARG;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    unsigned long long h[8];
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(h, ctx->d_stats, sizeof(h), hipMemcpyDeviceToHost));
+    for (int i = 0; i < 8; ++i) out8[i] = (int64_t)h[i];
+    out8[5] = ctx->rerun_total;
+    if (reset) {
+        HIPCHK(ctx, hipMemset(ctx->d_stats, 0, sizeof(h)));
+        ctx->rerun_total = 0;
+    }
+    return GWFA_OK;
+}
+
+}  // extern "C"

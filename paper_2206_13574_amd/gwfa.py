@@ -1,0 +1,303 @@
+"""Python binding of the HIP graph wavefront alignment library (libgwfa.so).
+
+Argument marshalling only: every step of the alignment runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  If the built
+library is missing this module raises at import; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgwfa.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2206_13574_amd/build.py "
+                      "(or __graft_entry__.build()); there is no fallback path")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- error / status codes (include/gwfa.h) ---------------------------------
+OK = 0
+ERR_ARG, ERR_VERTEX, ERR_ALPHABET, ERR_EMPTY_LABEL = -1, -2, -3, -4
+ERR_NOMEM, ERR_DEVICE, ERR_PATH_CAP, ERR_UNSUPPORTED = -5, -6, -7, -8
+ST_OK, ST_MAX_SCORE, ST_ARENA, ST_BAD_INPUT = 0, 1, 2, 3
+PRUNE_NONE, PRUNE_HEURISTIC, PRUNE_LEARNED = 0, 1, 2
+
+RESULT_DTYPE = np.dtype([("dist", "<i4"), ("end_v", "<i4"), ("end_off", "<i4"), ("status", "<i4"),
+                         ("path_off", "<i8"), ("path_len", "<i4"), ("n_scores", "<i4"), ("work", "<i8")])
+assert RESULT_DTYPE.itemsize == 40
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("prune", ctypes.c_int32), ("a_diff", ctypes.c_int32), ("keep_threshold", ctypes.c_float),
+                ("traceback", ctypes.c_int32), ("max_score", ctypes.c_int32), ("end_vertex", ctypes.c_int32),
+                ("mlp_gate", ctypes.c_int32), ("mlp_period", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_i32, _i64 = ctypes.c_int32, ctypes.c_int64
+
+_SIGS = {
+    "gwfa_opts_default": (None, [ctypes.POINTER(Opts)]),
+    "gwfa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "gwfa_last_error": (ctypes.c_char_p, [_P]),
+    "gwfa_ctx_create": (ctypes.c_int, [ctypes.c_int, _P, ctypes.POINTER(_P)]),
+    "gwfa_ctx_destroy": (None, [_P]),
+    "gwfa_ctx_config": (ctypes.c_int, [_P, _i32, _i32, _i32, _i32, _i32]),
+    "gwfa_graph_create": (ctypes.c_int, [_P, _i32, _P, _P, _i64, _P, _P, ctypes.POINTER(_P)]),
+    "gwfa_graph_destroy": (None, [_P]),
+    "gwfa_pack_dev": (ctypes.c_int, [_P, _P, _i64, _P, _P, _P]),
+    "gwfa_packed_words": (_i64, [_i64]),
+    "gwfa_align_batch": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64, _P]),
+    "gwfa_align_batch_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
+                                            _P, _P]),
+    "gwfa_mlp_load": (ctypes.c_int, [_P, _P, _i64, _P]),
+    "gwfa_stats": (ctypes.c_int, [_P, _P, _i32]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class GwfaError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str = ""):
+        self.code = code
+        msg = f"{where}: {_lib.gwfa_strerror(code).decode()} ({code})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+def _check(code: int, where: str, ctx=None):
+    if code != OK:
+        detail = _lib.gwfa_last_error(ctx).decode() if ctx else ""
+        raise GwfaError(code, where, detail)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(_P)
+
+
+def _tptr(t):
+    return _P(t.data_ptr()) if t is not None else None
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def opts(prune: int = PRUNE_NONE, a_diff: int = 0, keep_threshold: float = 0.0, traceback: bool = True,
+         max_score: int = -1, end_vertex: int = -1, mlp_gate: int = 0, mlp_period: int = 1) -> Opts:
+    o = Opts()
+    _lib.gwfa_opts_default(ctypes.byref(o))
+    o.prune, o.a_diff, o.keep_threshold = int(prune), int(a_diff), float(keep_threshold)
+    o.traceback, o.max_score, o.end_vertex = int(bool(traceback)), int(max_score), int(end_vertex)
+    o.mlp_gate, o.mlp_period = int(mlp_gate), int(mlp_period)
+    return o
+
+
+def packed_words(n_bases: int) -> int:
+    return int(_lib.gwfa_packed_words(int(n_bases)))
+
+
+class Context:
+    """A library context on a CUDA/HIP device, running on torch's current
+    stream of that device (or an explicit torch stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = int(device)
+        self.tdev = torch.device("cuda", self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.tdev)
+        h = _P()
+        _check(_lib.gwfa_ctx_create(self.device, _P(self.stream.cuda_stream), ctypes.byref(h)), "gwfa_ctx_create")
+        self.h = h
+        self._mlp = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.gwfa_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def config(self, lanes: int = 256, groups: int = 0, dir_log2_max: int = 16, list_cap: int = 1 << 15,
+               dir_factor: int = 16):
+        _check(_lib.gwfa_ctx_config(self.h, lanes, groups, dir_log2_max, list_cap, dir_factor), "gwfa_ctx_config",
+               self.h)
+
+    def stats(self, reset: bool = False) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        _check(_lib.gwfa_stats(self.h, _np_ptr(out), int(reset)), "gwfa_stats", self.h)
+        keys = ["entries", "crossings", "pages", "chunks", "admitted", "reruns", "mlp_evals", "pruned"]
+        return dict(zip(keys, out.tolist()))
+
+    def mlp_load(self, bf16_weights: np.ndarray, feat_scale: np.ndarray):
+        w = np.ascontiguousarray(bf16_weights, dtype=np.uint16)
+        sc = np.ascontiguousarray(feat_scale, dtype=np.float32)
+        _check(_lib.gwfa_mlp_load(self.h, _np_ptr(w), len(w), _np_ptr(sc)), "gwfa_mlp_load", self.h)
+
+
+class Graph:
+    """Graph uploaded to the device (packed labels + out-edge CSR)."""
+
+    def __init__(self, ctx: Context, seq, seg_off, edge_src, edge_dst):
+        self.ctx = ctx
+        seq = np.ascontiguousarray(np.frombuffer(seq, dtype=np.uint8) if isinstance(seq, (bytes, bytearray))
+                                   else seq, dtype=np.uint8)
+        seg_off = np.ascontiguousarray(seg_off, dtype=np.int64)
+        src = np.ascontiguousarray(edge_src, dtype=np.int32)
+        dst = np.ascontiguousarray(edge_dst, dtype=np.int32)
+        self.n_vtx = len(seg_off) - 1
+        h = _P()
+        _check(_lib.gwfa_graph_create(ctx.h, self.n_vtx, _np_ptr(seq), _np_ptr(seg_off), len(src), _np_ptr(src),
+                                      _np_ptr(dst), ctypes.byref(h)), "gwfa_graph_create", ctx.h)
+        self.h = h
+
+    @classmethod
+    def of(cls, ctx: Context, g) -> "Graph":
+        return cls(ctx, g.seq, g.seg_off, g.edge_src, g.edge_dst)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.gwfa_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class DeviceBatch:
+    """Queries resident in device memory (torch tensors)."""
+    ascii: object        # uint8 [n_bases]
+    packed: object       # int64 [packed_words]
+    read_off: object     # int64 [n+1]
+    v_start: object      # int32 [n]
+    order: object        # int32 [n] longest first
+    n: int
+    bases: int
+
+
+def upload_reads(ctx: Context, seq: np.ndarray, off: np.ndarray, v_start: np.ndarray) -> DeviceBatch:
+    torch = ctx.torch
+    seq = np.ascontiguousarray(seq, dtype=np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    vs = np.ascontiguousarray(v_start, dtype=np.int32)
+    n = len(vs)
+    lens = off[1:] - off[:-1]
+    order = np.argsort(-lens, kind="stable").astype(np.int32)
+    dev = ctx.tdev
+    return DeviceBatch(
+        ascii=torch.from_numpy(seq if len(seq) else np.zeros(1, np.uint8)).to(dev),
+        packed=torch.zeros(packed_words(len(seq)), dtype=torch.int64, device=dev),
+        read_off=torch.from_numpy(off).to(dev),
+        v_start=torch.from_numpy(vs if n else np.zeros(1, np.int32)).to(dev),
+        order=torch.from_numpy(order if n else np.zeros(1, np.int32)).to(dev),
+        n=n, bases=int(len(seq)))
+
+
+@dataclass
+class DeviceOut:
+    res: object          # uint8 [n*40]
+    path: object         # int32 [path_cap] or None
+    path_used: object    # int64 [1]
+    err: object          # int32 [1]
+
+
+def alloc_out(ctx: Context, n: int, path_cap: int) -> DeviceOut:
+    torch = ctx.torch
+    dev = ctx.tdev
+    return DeviceOut(res=torch.zeros(max(n, 1) * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev),
+                     path=torch.zeros(path_cap, dtype=torch.int32, device=dev) if path_cap > 0 else None,
+                     path_used=torch.zeros(1, dtype=torch.int64, device=dev),
+                     err=torch.zeros(1, dtype=torch.int32, device=dev))
+
+
+def pack_dev(ctx: Context, batch: DeviceBatch, err) -> None:
+    """ASCII -> 2-bit packing of the queries on the device."""
+    _check(_lib.gwfa_pack_dev(ctx.h, _tptr(batch.ascii), batch.bases, _tptr(batch.packed), _tptr(err),
+                              _P(ctx.stream.cuda_stream)), "gwfa_pack_dev", ctx.h)
+
+
+def align_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts) -> None:
+    """Aligns a device-resident batch (already packed) on ctx's stream."""
+    path_cap = int(out.path.numel()) if out.path is not None else 0
+    _check(_lib.gwfa_align_batch_dev(ctx.h, graph.h, batch.n, _tptr(batch.packed), _tptr(batch.read_off),
+                                     _tptr(batch.v_start), _tptr(batch.order), ctypes.byref(o), _tptr(out.res),
+                                     _tptr(out.path), path_cap, _tptr(out.path_used),
+                                     _P(ctx.stream.cuda_stream)), "gwfa_align_batch_dev", ctx.h)
+
+
+def step_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts) -> None:
+    """One pass of the whole path on resident queries: pack, then align."""
+    pack_dev(ctx, batch, out.err)
+    align_dev(ctx, graph, batch, out, o)
+
+
+def fetch(out: DeviceOut, n: int):
+    """Results (structured numpy array) and the path buffer (numpy)."""
+    res = np.frombuffer(out.res.cpu().numpy().tobytes(), dtype=RESULT_DTYPE)[:n].copy()
+    used = int(out.path_used.cpu().item())
+    path = out.path[:min(used, out.path.numel())].cpu().numpy() if out.path is not None else None
+    return res, path, used
+
+
+def align(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_cap: int = None):
+    """Convenience: host queries in, results out (through the device-side
+    entry points).  Returns (results, paths) with paths a list of int32
+    arrays (or None when traceback is off)."""
+    if o is None:
+        o = opts()
+    seq = np.ascontiguousarray(np.frombuffer(seq, dtype=np.uint8) if isinstance(seq, (bytes, bytearray)) else seq,
+                               dtype=np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    n = len(off) - 1
+    batch = upload_reads(ctx, seq, off, v_start)
+    if path_cap is None:
+        path_cap = (int(off[-1]) + 64 * n) if o.traceback else 0
+    out = alloc_out(ctx, n, path_cap)
+    step_dev(ctx, graph, batch, out, o)
+    ctx.torch.cuda.synchronize(ctx.tdev)
+    if int(out.err.cpu().item()) != 0:
+        raise GwfaError(ERR_ALPHABET, "gwfa_pack_dev")
+    res, path, used = fetch(out, n)
+    paths = None
+    if o.traceback:
+        if used > path_cap:
+            raise GwfaError(ERR_PATH_CAP, "align", f"needs {used} ids, buffer {path_cap}")
+        paths = [path[r["path_off"]:r["path_off"] + r["path_len"]] if r["path_off"] >= 0 else None for r in res]
+    return res, paths
+
+
+def align_host(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_cap: int = 0):
+    """The host-buffer entry point gwfa_align_batch (validates everything on
+    the host first)."""
+    if o is None:
+        o = opts()
+    seq = np.ascontiguousarray(np.frombuffer(seq, dtype=np.uint8) if isinstance(seq, (bytes, bytearray)) else seq,
+                               dtype=np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    vs = np.ascontiguousarray(v_start, dtype=np.int32)
+    n = len(off) - 1
+    res = np.zeros(max(n, 1), dtype=RESULT_DTYPE)
+    path = np.zeros(max(path_cap, 1), dtype=np.int32)
+    needed = ctypes.c_int64(0)
+    code = _lib.gwfa_align_batch(ctx.h, graph.h, n, _np_ptr(seq), _np_ptr(off), _np_ptr(vs), ctypes.byref(o),
+                                 _np_ptr(res), _np_ptr(path) if path_cap else None, int(path_cap),
+                                 ctypes.byref(needed))
+    return code, res[:n], path[:path_cap], int(needed.value)

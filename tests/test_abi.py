@@ -1,0 +1,50 @@
+"""The C ABI library loads and exports every symbol include/gwfa.h declares
+(CPU only: no compute call needs a GPU here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gwfa.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gwfa_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for need in ("gwfa_ctx_create", "gwfa_graph_create", "gwfa_align_batch", "gwfa_align_batch_dev",
+                 "gwfa_pack_dev", "gwfa_mlp_load", "gwfa_strerror"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2206_13574_amd import gwfa
+    lib = ctypes.CDLL(gwfa.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding wraps exactly the declared calls
+    assert sorted(gwfa.exported_symbols()) == declared_functions()
+
+
+def test_host_only_calls():
+    from paper_2206_13574_amd import gwfa
+    assert gwfa.packed_words(0) == 2 and gwfa.packed_words(1) == 3 and gwfa.packed_words(64) == 4
+    o = gwfa.opts()
+    assert (o.prune, o.traceback, o.max_score, o.end_vertex, o.mlp_period) == (0, 1, -1, -1, 1)
+    assert gwfa.RESULT_DTYPE.itemsize == 40
+    for code in range(-8, 1):
+        assert gwfa._lib.gwfa_strerror(code)
+    # argument checks that return before touching a device
+    h = ctypes.c_void_p()
+    assert gwfa._lib.gwfa_ctx_create(-1, None, ctypes.byref(h)) == gwfa.ERR_ARG
+    assert gwfa._lib.gwfa_ctx_create(0, None, None) == gwfa.ERR_ARG
+    assert gwfa._lib.gwfa_align_batch(None, None, 0, None, None, None, None, None, None, 0, None) == gwfa.ERR_ARG
+    assert gwfa._lib.gwfa_graph_create(None, 1, None, None, 0, None, None, None) == gwfa.ERR_ARG
+    stats = np.zeros(8, dtype=np.int64)
+    assert gwfa._lib.gwfa_stats(None, stats.ctypes.data_as(ctypes.c_void_p), 0) == gwfa.ERR_ARG
