@@ -78,6 +78,27 @@ def cpu_baseline(g, r, seconds: float = 15.0, seed: int = 11):
                       f"the injected edit count, OpenMP over reads"}
 
 
+def recorded_traffic(workload: str, lanes: int):
+    """HBM traffic per launch of k_align from the committed rocprofv3 summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), only while
+    the kernel source is the one that was profiled; else None."""
+    import glob
+    import hashlib
+    import re
+    root = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(root, "paper_2206_13574_amd", "csrc", "gwfa_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for f in sorted(glob.glob(os.path.join(root, "profiles", "k_align_*.md"))):
+        m = re.search(r"```json\n(.*?)\n```", open(f).read(), re.S)
+        if not m:
+            continue
+        d = json.loads(m.group(1))
+        if d.get("workload") == workload and d.get("kernel_src_sha256_16") == sha and \
+                d.get("kernel", "").endswith(f"<{lanes}>"):
+            return d["traffic_bytes_per_launch"], os.path.relpath(f, root)
+    return None, None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +189,7 @@ def main():
     alg_bytes = entries * B_ENTRY + chunks * B_CHUNK + cross * B_CROSS
     align_avg_s = float(np.mean(align_ms)) / 1000.0
     achieved = alg_bytes / align_avg_s / 1e9
+    traffic, traffic_src = recorded_traffic(args.workload, cfg["lanes"])
     pack_avg_s = float(np.mean(pack_ms)) / 1000.0
     pack_bytes = bases * 1.25
     line = {
@@ -189,7 +211,7 @@ def main():
                    "a_diff": args.a_diff if args.prune == 1 else None, "traceback": bool(o.traceback),
                    "lanes_per_read": cfg["lanes"], "groups": cfg.get("groups", 0)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
                      "kernel": "k_align (persistent, one workgroup per read)",
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": align_avg_s * 1000.0,
                      "entries_per_launch": entries, "chunks_per_launch": chunks,
