@@ -84,7 +84,9 @@ typedef struct {
     int32_t path_len;       /* vertices in the walk (start ... end_v)              */
     int32_t n_scores;       /* scores run (dist + 1 on success)                    */
     int64_t work;           /* sum over scores s of |F_s| (entries after extension) */
-} gwfa_result;              /* 40 bytes */
+    int64_t t_begin;        /* device wall clock (100 MHz ticks) when the query   */
+    int64_t t_end;          /* was taken from the work queue / finished           */
+} gwfa_result;              /* 56 bytes */
 
 /* Default options: exact, traceback on, unbounded, extension mode. */
 void gwfa_opts_default(gwfa_opts *opts);
@@ -96,17 +98,19 @@ const char *gwfa_strerror(int code);
 const char *gwfa_last_error(const gwfa_ctx *ctx);
 
 /* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t on
- * that device or NULL for a library-owned stream; the library never destroys a
- * caller's stream.  Working memory is allocated on the first alignment call. */
+ * that device, or NULL for the HIP null stream (which orders with every
+ * blocking stream of the device); the library never destroys a stream.
+ * Working memory is allocated (and cleared, synchronously) on the first
+ * alignment call. */
 int gwfa_ctx_create(int device, void *hip_stream, gwfa_ctx **out);
 void gwfa_ctx_destroy(gwfa_ctx *ctx);
 
 /* Working-memory / launch configuration (used by the autotuner).
- *   lanes_per_query: 64, 128 or 256 threads cooperate on one query;
+ *   lanes_per_query: 64, 128, 256 or 512 threads cooperate on one query;
  *   n_groups: persistent workgroups (0 = one per compute unit x 4);
  *   dir_log2_max: log2 of the largest per-query diagonal-page directory
  *                 (each page holds 32 diagonals of one vertex; 10..22);
- *   list_cap: capacity of each per-query wavefront list (entries);
+ *   list_cap: capacity of each per-query wavefront list (entries, even);
  *   dir_factor: initial directory slots per 32 query bases (power of two).
  * Returns GWFA_ERR_ARG on a value out of range.  Frees working memory, which
  * is reallocated on the next call. */
@@ -130,7 +134,7 @@ void gwfa_graph_destroy(gwfa_graph *g);
 
 /* Packs n_bases ASCII bases (device) into 2-bit words (device, at least
  * gwfa_packed_words(n_bases) words: the 2-word zero tail is written too) on
- * `hip_stream` (NULL = context stream).  A base outside ACGT/acgt sets
+ * `hip_stream` (NULL = the context's stream).  A base outside ACGT/acgt sets
  * *d_err (device int32, the caller clears it first) to GWFA_ERR_ALPHABET;
  * such bases are packed as A.  Asynchronous. */
 int gwfa_pack_dev(gwfa_ctx *ctx, const uint8_t *d_ascii, int64_t n_bases, uint64_t *d_packed,
@@ -181,8 +185,11 @@ int gwfa_mlp_load(gwfa_ctx *ctx, const uint16_t *bf16_weights, int64_t n, const 
  * every query): [0] wavefront entries (sum |F_s|), [1] crossings admitted,
  * [2] pages created, [3] 32-base compare chunks in the extension,
  * [4] expansion candidates admitted, [5] queries re-run for memory,
- * [6] MLP evaluations, [7] entries dropped by pruning. */
-int gwfa_stats(gwfa_ctx *ctx, int64_t *out8, int32_t reset);
+ * [6] MLP evaluations, [7] entries dropped by pruning, [8] scores run,
+ * [9]..[12] device wall-clock ticks (100 MHz) summed over queries spent in
+ * the expansion+extension pass, the crossing rounds, the crossing merge and
+ * the pruning pass, [13]..[15] reserved.  out16 receives 16 values. */
+int gwfa_stats(gwfa_ctx *ctx, int64_t *out16, int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -26,25 +26,32 @@ struct Tier {
     int32_t dir_log2_max = 16;
     int32_t list_cap = 1 << 15;
     int32_t cand_cap = 1 << 16;
+    int32_t sort_cap = 1 << 15;
     int32_t groups = 0;
     char* arena = nullptr;
     int64_t stride = 0;
-    int64_t o_dir = 0, o_pages = 0, o_mkey = 0, o_mval = 0, o_tv = 0, o_tt = 0, o_lists = 0, o_cand = 0;
+    int64_t o_hdr = 0, o_dir = 0, o_pages = 0, o_mkey = 0, o_tv = 0, o_tt = 0, o_lists = 0, o_cand = 0, o_sort = 0;
 };
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// One arena per persistent workgroup: header (generation counter), page
+// directory, record pages, trace map + trace array, two wavefront lists,
+// crossing candidates, sort scratch.
 void layout(Tier& t) {
     const int64_t C = (int64_t)1 << t.dir_log2_max;
+    t.sort_cap = 1;
+    while (t.sort_cap < t.list_cap) t.sort_cap <<= 1;
     int64_t o = 0;
+    t.o_hdr = o;   o = align_up(o + 256, 512);
     t.o_dir = o;   o = align_up(o + C * 8, 512);
     t.o_pages = o; o = align_up(o + C * 512, 512);
     t.o_mkey = o;  o = align_up(o + C * 8, 256);
-    t.o_mval = o;  o = align_up(o + C * 4, 256);
-    t.o_tv = o;    o = align_up(o + (C / 2) * 4, 256);
-    t.o_tt = o;    o = align_up(o + (C / 2) * 4, 256);
-    t.o_lists = o; o = align_up(o + (int64_t)2 * 6 * t.list_cap * 4, 256);
-    t.o_cand = o;  o = align_up(o + (int64_t)5 * t.cand_cap * 4, 4096);
+    t.o_tv = o;    o = align_up(o + C * 4, 256);
+    t.o_tt = o;    o = align_up(o + C * 4, 256);
+    t.o_lists = o; o = align_up(o + (int64_t)2 * 9 * t.list_cap * 4, 256);
+    t.o_cand = o;  o = align_up(o + (int64_t)4 * t.cand_cap * 4, 256);
+    t.o_sort = o;  o = align_up(o + (int64_t)t.sort_cap * 12, 4096);
     t.stride = o;
 }
 
@@ -119,6 +126,11 @@ int ensure_tier(gwfa_ctx* ctx, int ti) {
         ctx->err = "arena allocation of " + std::to_string(bytes) + " bytes failed";
         return GWFA_ERR_NOMEM;
     }
+    // generation 0 everywhere: record words of generation 0 read as "never
+    // seen" for every query (queries use generations 1, 2, ...)
+    e = hipMemset(t.arena, 0, bytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();   // finished before any kernel on any stream uses it
+    if (e != hipSuccess) return dev_fail(ctx, e, "arena clear");
     return GWFA_OK;
 }
 
@@ -179,17 +191,16 @@ int gwfa_ctx_create(int device, void* hip_stream, gwfa_ctx** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->n_cu = prop.multiProcessorCount;
-    if (hip_stream) {
-        c->stream = (hipStream_t)hip_stream;
-    } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return GWFA_ERR_DEVICE; }
-        c->own_stream = true;
-    }
+    // NULL selects the HIP null stream, which orders with every blocking
+    // stream of the device (e.g. the default stream of a framework)
+    c->stream = (hipStream_t)hip_stream;
+    c->own_stream = false;
     bool ok = hipMalloc((void**)&c->d_queue, sizeof(int32_t)) == hipSuccess &&
               hipMalloc((void**)&c->d_cursor, sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc((void**)&c->d_retry_count, sizeof(int32_t)) == hipSuccess &&
-              hipMalloc((void**)&c->d_stats, 8 * sizeof(unsigned long long)) == hipSuccess;
-    if (ok) ok = hipMemset(c->d_stats, 0, 8 * sizeof(unsigned long long)) == hipSuccess;
+              hipMalloc((void**)&c->d_stats, 16 * sizeof(unsigned long long)) == hipSuccess;
+    if (ok) ok = hipMemset(c->d_stats, 0, 16 * sizeof(unsigned long long)) == hipSuccess &&
+                 hipDeviceSynchronize() == hipSuccess;
     if (!ok) { gwfa_ctx_destroy(c); return GWFA_ERR_NOMEM; }
     set_tiers(c, 16, 1 << 15);
     *out = c;
@@ -215,10 +226,10 @@ void gwfa_ctx_destroy(gwfa_ctx* c) {
 int gwfa_ctx_config(gwfa_ctx* c, int32_t lanes, int32_t n_groups, int32_t dir_log2_max, int32_t list_cap,
                     int32_t dir_factor) {
     if (!c) return GWFA_ERR_ARG;
-    if (lanes != 64 && lanes != 128 && lanes != 256) return GWFA_ERR_ARG;
+    if (lanes != 64 && lanes != 128 && lanes != 256 && lanes != 512) return GWFA_ERR_ARG;
     if (n_groups < 0 || n_groups > (1 << 20)) return GWFA_ERR_ARG;
     if (dir_log2_max < 10 || dir_log2_max > 22) return GWFA_ERR_ARG;
-    if (list_cap < 1024 || list_cap > (1 << 24)) return GWFA_ERR_ARG;
+    if (list_cap < 1024 || list_cap > (1 << 24) || (list_cap & 1)) return GWFA_ERR_ARG;
     if (dir_factor < 1 || dir_factor > 4096 || (dir_factor & (dir_factor - 1))) return GWFA_ERR_ARG;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
@@ -373,9 +384,9 @@ int gwfa_align_batch_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, co
         A.order = order; A.n_reads = n;
         A.retry = (ti + 1 < N_TIERS) ? ctx->d_retry[ti & 1] : nullptr;
         A.arena = t.arena; A.arena_stride = t.stride;
-        A.dir_log2_max = t.dir_log2_max; A.list_cap = t.list_cap; A.cand_cap = t.cand_cap;
-        A.o_dir = t.o_dir; A.o_pages = t.o_pages; A.o_mkey = t.o_mkey; A.o_mval = t.o_mval;
-        A.o_tv = t.o_tv; A.o_tt = t.o_tt; A.o_lists = t.o_lists; A.o_cand = t.o_cand;
+        A.dir_log2_max = t.dir_log2_max; A.list_cap = t.list_cap; A.cand_cap = t.cand_cap; A.sort_cap = t.sort_cap;
+        A.o_hdr = t.o_hdr; A.o_dir = t.o_dir; A.o_pages = t.o_pages; A.o_mkey = t.o_mkey;
+        A.o_tv = t.o_tv; A.o_tt = t.o_tt; A.o_lists = t.o_lists; A.o_cand = t.o_cand; A.o_sort = t.o_sort;
         const int groups = std::min<int64_t>(t.groups, n);
         HIPCHK(ctx, gwfa_launch_align(A, ctx->lanes, groups, st));
         if (ti + 1 == N_TIERS) break;
@@ -486,14 +497,14 @@ int gwfa_mlp_load(gwfa_ctx* ctx, const uint16_t* w, int64_t n, const float* scal
     return GWFA_OK;
 }
 
-int gwfa_stats(gwfa_ctx* ctx, int64_t* out8, int32_t reset) {
-    if (!ctx || !out8) return GWFA_ERR_ARG;
+int gwfa_stats(gwfa_ctx* ctx, int64_t* out16, int32_t reset) {
+    if (!ctx || !out16) return GWFA_ERR_ARG;
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    unsigned long long h[8];
+    unsigned long long h[16];
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     HIPCHK(ctx, hipMemcpy(h, ctx->d_stats, sizeof(h), hipMemcpyDeviceToHost));
-    for (int i = 0; i < 8; ++i) out8[i] = (int64_t)h[i];
-    out8[5] = ctx->rerun_total;
+    for (int i = 0; i < 16; ++i) out16[i] = (int64_t)h[i];
+    out16[5] = ctx->rerun_total;
     if (reset) {
         HIPCHK(ctx, hipMemset(ctx->d_stats, 0, sizeof(h)));
         ctx->rerun_total = 0;

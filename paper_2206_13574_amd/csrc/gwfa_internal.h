@@ -36,8 +36,8 @@ struct KArgs {
     // working memory: one arena per workgroup
     char* arena;
     int64_t arena_stride;
-    int32_t dir_log2_max, dir_factor, list_cap, cand_cap;
-    int64_t o_dir, o_pages, o_mkey, o_mval, o_tv, o_tt, o_lists, o_cand;
+    int32_t dir_log2_max, dir_factor, list_cap, cand_cap, sort_cap;
+    int64_t o_hdr, o_dir, o_pages, o_mkey, o_tv, o_tt, o_lists, o_cand, o_sort;
 };
 
 hipError_t gwfa_launch_align(const KArgs& A, int lanes, int groups, hipStream_t st);

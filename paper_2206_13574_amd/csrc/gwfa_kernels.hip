@@ -3,33 +3,34 @@
 //
 // One persistent workgroup aligns one query at a time, taking queries from a
 // device work queue.  Per score s it runs the paper's loop (Section 2.4):
-//   EXTEND  (Algorithm 2): slide every diagonal of F_s along its vertex by the
-//           exact-match run (2-bit packed XOR + count-leading-zeros, 32 bases
-//           per step); a diagonal reaching the end of vertex v creates
-//           (u, k+|v|) at offset 0 on every out-edge (v,u) not seen before,
-//           at the same score, and those are extended in further rounds;
-//   END     (extension mode): stop at the first score where some cell of the
-//           wavefront has consumed the whole query;
-//   PRUNE   (Algorithm 4, optional) or the learned keep/drop network;
-//   EXPAND  (Algorithm 3): insertion / deletion / mismatch candidates of
-//           every diagonal, merged per diagonal, admitted when they beat the
-//           diagonal's record.
+//   EXPAND  (Algorithm 3): insertion / deletion / mismatch candidates of every
+//           diagonal of F_s, merged per diagonal, admitted when they beat the
+//           diagonal's record;
+//   EXTEND  (Algorithm 2): every admitted diagonal slides along its vertex by
+//           the exact-match run (2-bit packed XOR + count-leading-zeros, 32
+//           bases per step); a diagonal reaching the end of vertex v creates
+//           (u, k+|v|) at offset 0 on every out-edge (v,u) not seen before, at
+//           the same score (cost 0), and those are extended in further rounds;
+//   END     (extension mode): stop at the first score at which a wavefront
+//           cell has consumed the whole query;
+//   PRUNE   (Algorithm 4, optional) or the learned keep/drop network.
 //
-// Per-query state lives in an HBM arena owned by the workgroup:
-//   * diagonal records (the paper's wavefront set H~, never cleared while a
-//     query runs): pages of 32 consecutive diagonals (v, 32p .. 32p+31),
-//     found through an open-addressing page directory keyed (v, p).  A page
-//     slot holds the furthest offset, the score stamp of the last time the
-//     diagonal was in a wavefront, and (walk length W, trace index t);
-//   * the wavefront F_s as a list of entries (v, k, off, W, t, page);
-//   * the crossing candidates of the current round;
-//   * the traceback array T and its de-duplication map M (Algorithm 5).
+// The wavefront F_s is a list sorted by (v, k).  The expansion is
+// owner-computes: output diagonal k' of vertex v is produced by the present
+// source with the smallest k among k'-1, k', k'+1, and those sources are the
+// source's neighbours in the sorted list, so the expansion reads no table
+// except at the two ends of a run of consecutive diagonals (where the record
+// of a diagonal outside F_s decides).  Outputs come out sorted (ordered block
+// scan) and are extended by the lane that produced them in the same pass.
+// Diagonals created by crossings are sorted (bitonic) and merged in.
 //
-// EXPAND is owner-computes: the output diagonal k' of vertex v is produced by
-// the present source with the smallest k among k'-1, k', k'+1 (present =
-// stamped with the current score), which gathers all three sources from the
-// page, so no atomics are needed and the result (largest offset, ties to the
-// larger W) does not depend on scheduling.
+// Records of the paper's wavefront set H~ (kept for the life of a query):
+// pages of 32 consecutive diagonals of one vertex, found through an
+// open-addressing directory keyed (v, k >> 5).  A record word is
+// (generation << 32 | offset): a word whose generation is not the current
+// query's is "never seen", so pages need no initialisation.  A record holds
+// the diagonal's offset when it left the wavefront (reached the vertex end or
+// was pruned) -- the only diagonals outside F_s that can still be candidates.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -40,28 +41,26 @@ namespace gwfa_dev {
 typedef unsigned long long ull;
 
 constexpr int PAGE = 32;
-constexpr int32_t ST_EMPTY = -1;
-constexpr int32_t ST_CLAIM = -2;
-constexpr int32_t ST_PRUNED = 0x40000000;
-
-constexpr int F_GROW = 1;   // directory / trace capacity exceeded: restart bigger
-constexpr int F_LIST = 2;   // list or candidate capacity exceeded: give up (re-run on a larger tier)
+constexpr int32_t CLAIM_BASE = 0x40000000;   // record value while a crossing round claims it
+constexpr int F_GROW = 1;   // directory / trace capacity exceeded: restart with a bigger one
+constexpr int F_LIST = 2;   // list / candidate capacity exceeded: re-run on a larger tier
+constexpr int XS_LDS = 1024;   // crossing entries sorted in LDS up to this many
 
 struct Page {
-    int32_t off[PAGE];
-    int32_t stamp[PAGE];
-    ull wt[PAGE];   // (W << 32) | (t + 1)
+    ull R[PAGE];    // (gen << 32) | record offset (or CLAIM_BASE + round)
+    ull Wc[PAGE];   // (gen << 32) | W: max walk length of a round's crossings
 };
 static_assert(sizeof(Page) == 512, "page layout");
 
-__device__ __forceinline__ ull pack_wt(int32_t W, int32_t t) {
-    return ((ull)(uint32_t)W << 32) | (ull)(uint32_t)(t + 1);
-}
-__device__ __forceinline__ int32_t wt_W(ull x) { return (int32_t)(x >> 32); }
-__device__ __forceinline__ int32_t wt_t(ull x) { return (int32_t)(uint32_t)(x & 0xffffffffull) - 1; }
+__device__ __forceinline__ ull mkR(uint32_t gen, int32_t r) { return ((ull)gen << 32) | (ull)(uint32_t)r; }
+__device__ __forceinline__ uint32_t rgen(ull w) { return (uint32_t)(w >> 32); }
+__device__ __forceinline__ int32_t rval(ull w) { return (int32_t)(uint32_t)(w & 0xffffffffull); }
 
 __device__ __forceinline__ ull dkey(int32_t v, int32_t kp) {
     return ((ull)(uint32_t)(v + 1) << 32) | (ull)(uint32_t)(kp + 0x40000000);
+}
+__device__ __forceinline__ ull skey(int32_t v, int32_t k) {   // sort key of a diagonal
+    return ((ull)(uint32_t)v << 32) | (ull)(uint32_t)(k + 0x40000000);
 }
 __device__ __forceinline__ uint32_t dhash(ull key) {
     return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 32);
@@ -76,17 +75,33 @@ __device__ __forceinline__ ull win32(const ull* __restrict__ w, int64_t p) {
     return (a << sh) | ((b >> 1) >> (63 - sh));
 }
 
-// LCP of q[qp ...] and segment[sp ...], at most lim bases.
+// LCP of q[qp ...] and label[sp ...], at most lim bases.  Each step
+// compares up to four 32-base windows whose loads are issued together, so a
+// long exact run costs one memory round trip per 128 bases.  Windows that
+// start at or past lim are not loaded (both stores end with two words of
+// padding, so a window starting inside the range stays in bounds).
 __device__ __forceinline__ int32_t lcp(const ull* __restrict__ qw, int64_t qp, const ull* __restrict__ sw,
                                        int64_t sp, int32_t lim, uint32_t& chunks) {
     int32_t l = 0;
     while (l < lim) {
-        const ull x = win32(qw, qp + l) ^ win32(sw, sp + l);
-        const int32_t m = x ? (int32_t)(__clzll((long long)x) >> 1) : 32;
-        ++chunks;
-        if (m >= lim - l) { l = lim; break; }
+        const int32_t rem = lim - l;
+        ull x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            x[j] = (32 * j < rem) ? (win32(qw, qp + l + 32 * j) ^ win32(sw, sp + l + 32 * j)) : 0ull;
+        int32_t m = 0;
+        bool stop = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!stop && 32 * j < rem) {
+                ++chunks;
+                if (x[j]) { m += (int32_t)(__clzll((long long)x[j]) >> 1); stop = true; }
+                else m += 32;
+            }
+        }
+        if (m >= rem) return lim;
         l += m;
-        if (m < 32) break;
+        if (stop) return l;
     }
     return l;
 }
@@ -94,7 +109,7 @@ __device__ __forceinline__ int32_t lcp(const ull* __restrict__ qw, int64_t qp, c
 __device__ int dir_find(const ull* __restrict__ dir, uint32_t mask, ull key) {
     uint32_t h = dhash(key) & mask;
     for (uint32_t p = 0; p <= mask; ++p) {
-        const ull c = dir[h];
+        const ull c = __hip_atomic_load(&dir[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (c == key) return (int)h;
         if (c == 0) return -1;
         h = (h + 1) & mask;
@@ -102,29 +117,20 @@ __device__ int dir_find(const ull* __restrict__ dir, uint32_t mask, ull key) {
     return -1;
 }
 
-__device__ int dir_insert(ull* dir, uint32_t mask, ull key, bool& inserted) {
+// Find-or-insert; counts insertions in *n_ins.  -1 when the table is full.
+__device__ int dir_insert(ull* dir, uint32_t mask, ull key, int* n_ins) {
     uint32_t h = dhash(key) & mask;
-    inserted = false;
     for (uint32_t p = 0; p <= mask; ++p) {
         const ull c = __hip_atomic_load(&dir[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (c == key) return (int)h;
         if (c == 0) {
             const ull old = atomicCAS(&dir[h], 0ull, key);
-            if (old == 0) { inserted = true; return (int)h; }
+            if (old == 0) { atomicAdd(n_ins, 1); return (int)h; }
             if (old == key) return (int)h;
         }
         h = (h + 1) & mask;
     }
     return -1;
-}
-
-__device__ __forceinline__ void page_init(Page* pg) {
-    int4* s = reinterpret_cast<int4*>(pg->stamp);
-#pragma unroll
-    for (int i = 0; i < PAGE / 4; ++i) s[i] = make_int4(ST_EMPTY, ST_EMPTY, ST_EMPTY, ST_EMPTY);
-    int4* w = reinterpret_cast<int4*>(pg->wt);
-#pragma unroll
-    for (int i = 0; i < PAGE / 2; ++i) w[i] = make_int4(0, 0, 0, 0);
 }
 
 // Exclusive prefix sum of x over the 64 lanes of the wave, plus the total.
@@ -140,8 +146,8 @@ __device__ __forceinline__ int wave_excl_scan(int x, int& total) {
     return incl - x;
 }
 
-// Reserves cnt consecutive slots from an LDS counter for every lane of the
-// wave (one atomic per wave).  Must be reached by all lanes of the wave.
+// Reserves cnt consecutive slots of an LDS counter (one atomic per wave,
+// order between waves unspecified).  All lanes of the wave must call it.
 __device__ __forceinline__ int wave_alloc(int cnt, int* counter) {
     int total;
     const int ex = wave_excl_scan(cnt, total);
@@ -151,9 +157,28 @@ __device__ __forceinline__ int wave_alloc(int cnt, int* counter) {
     return base + ex;
 }
 
-struct Lists {
-    int32_t *v, *k, *o, *w, *t, *d;
-};
+// Exclusive prefix sum over the whole block in thread order (keeps lists
+// sorted).  All threads must call it.
+template <int BLOCK>
+__device__ __forceinline__ int block_excl_scan(int x, int& total, int* scan) {
+    constexpr int NW = BLOCK / 64;
+    int wt;
+    const int ex = wave_excl_scan(x, wt);
+    const int w = threadIdx.x >> 6;
+    if (NW == 1) { total = wt; return ex; }
+    if (__lane_id() == 0) scan[w] = wt;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const int y = scan[i];
+        off += (i < w) ? y : 0;
+        tot += y;
+    }
+    __syncthreads();
+    total = tot;
+    return off + ex;
+}
 
 // Reads a shared word that other threads may update in the phase that just
 // ended, so that every thread takes the same decision: barrier, read,
@@ -165,172 +190,441 @@ __device__ __forceinline__ int read_uniform(const int& x) {
     return v;
 }
 
+// A wavefront list: per entry the diagonal (v, k), its offset o, walk length
+// W, trace index t, record page d, and the label length l and base b of v.
+struct Lists {
+    int32_t *v, *k, *o, *w, *t, *d, *l;
+    int64_t* b;
+};
+
 struct Shared {
     int32_t read;
-    int32_t n[2];
+    int32_t n_out;    // entries in the list being built (outputs, then crossing entries)
     int32_t ncand;
-    int32_t dirn;
-    int32_t tn;
+    int32_t dirn;     // pages created
+    int32_t mn;       // trace entries created
     int32_t flags;
     int32_t found;
     int32_t amax;
-    int32_t tend;
+    int32_t imax;
     int32_t dropped;
+    int32_t tend;
+    uint32_t gen;
     ull endkey;
     ull chunks;
     ull cross;
     ull adm;
     ull mlp;
+    ull tick[4];      // wall-clock ticks per phase (thread 0)
+    int32_t scan[16];
+    ull skeys[XS_LDS];
+    int32_t sidx[XS_LDS];
+    int32_t xcnt[XS_LDS];   // merge: main-list entries below each crossing entry
+    ull skeys2[64];         // crossing keys sorted by rank counting (small sets)
 };
+
+// Per-query view of the arena and of the read.
+struct Q {
+    const ull* rd;
+    int64_t q0;
+    int32_t qlen, vs;
+    ull* dir;
+    Page* pages;
+    ull* mkey;
+    int32_t* Tv;
+    int32_t* Tt;
+    uint32_t mask;
+    uint32_t gen;
+    bool tb, prune;
+};
+
+// Algorithm 5: T gets (v, t) unless the pair is already there; the index of
+// the pair's slot in the de-duplication map is its trace index.
+__device__ __forceinline__ int32_t trace_push(const Q& q, Shared& S, int32_t v, int32_t tprev) {
+    const int ms = dir_insert(q.mkey, q.mask, dkey(v, tprev), &S.mn);
+    if (ms < 0) { atomicOr(&S.flags, F_GROW); return -1; }
+    // the slot's (v, tprev) is fixed by its key, so every inserter may write it
+    q.Tv[ms] = v;
+    q.Tt[ms] = tprev;
+    return ms;
+}
+
+// Records an extended diagonal: its record word when it is new or reached
+// the vertex end, the end test and the pruning reductions; returns the number
+// of out-edges to cross (0 unless the vertex end was reached).
+__device__ __forceinline__ int record_entry(const KArgs& A, const Q& q, Shared& S, int32_t v, int32_t k,
+                                            int32_t o, int32_t W, int32_t d, bool mark, int32_t Lv) {
+    const int32_t i = k + o;
+    if (mark || o == Lv) q.pages[d].R[k & 31] = mkR(q.gen, o);
+    if (i == q.qlen) {
+        S.found = 1;
+        if (o >= 1 || v == q.vs) atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
+    }
+    if (q.prune) {
+        atomicMax(&S.amax, i + W);
+        atomicMax(&S.imax, i);
+    }
+    return (o == Lv) ? (A.out_off[v + 1] - A.out_off[v]) : 0;
+}
+
+// Extends one admitted diagonal (Algorithm 2) and records it.
+__device__ __forceinline__ int extend_entry(const KArgs& A, const Q& q, Shared& S, int32_t v, int32_t k,
+                                            int32_t& o, int32_t& W, int32_t d, bool mark, int64_t sb,
+                                            int32_t Lv, uint32_t& chunks) {
+    const int32_t i = k + o;
+    const int32_t lim = min(q.qlen - i, Lv - o);
+    const int32_t l = lcp(q.rd, q.q0 + i, A.seg, sb + o, lim, chunks);
+    o += l;
+    W += l;
+    return record_entry(A, q, S, v, k, o, W, d, mark, Lv);
+}
+
+// Bitonic sort of n keys (+ payload) in place, ascending; n is a power of 2.
+template <int BLOCK>
+__device__ void bitonic(ull* keys, int32_t* idx, int n) {
+    for (int kk = 2; kk <= n; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += BLOCK) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const ull a = keys[i], b = keys[p];
+                    const bool up = (i & kk) == 0;
+                    if ((a > b) == up) {
+                        keys[i] = b; keys[p] = a;
+                        const int32_t t = idx[i]; idx[i] = idx[p]; idx[p] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Number of entries of list L[0, n) whose key is below key.
+__device__ __forceinline__ int32_t lower_bound_list(const Lists& L, int32_t n, ull key) {
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (skey(L.v[mid], L.k[mid]) < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ int32_t lower_bound_keys(const ull* keys, int32_t n, ull key) {
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (keys[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void copy_entry(const Lists& a, int32_t i, const Lists& b, int32_t j) {
+    b.v[j] = a.v[i]; b.k[j] = a.k[i]; b.o[j] = a.o[i]; b.w[j] = a.w[i]; b.t[j] = a.t[i]; b.d[j] = a.d[i];
+    b.l[j] = a.l[i]; b.b[j] = a.b[i];
+}
 
 template <int BLOCK>
 __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shared& S) {
     const int tid = threadIdx.x;
-    const int64_t q0 = A.rd_off[r];
-    const int32_t qlen = (int32_t)(A.rd_off[r + 1] - q0);
-    const int32_t vs = A.v_start[r];
+    Q q;
+    q.rd = A.rd;
+    q.q0 = A.rd_off[r];
+    q.qlen = (int32_t)(A.rd_off[r + 1] - q.q0);
+    q.vs = A.v_start[r];
     gwfa_result* out = A.res + r;
-    if (vs < 0 || vs >= A.n_vtx) {
+    const int64_t t_begin = (int64_t)wall_clock64();
+    if (q.vs < 0 || q.vs >= A.n_vtx) {
         if (tid == 0) {
+            out->t_begin = t_begin; out->t_end = t_begin;
             out->dist = -1; out->end_v = -1; out->end_off = -1; out->status = GWFA_ST_BAD_INPUT;
             out->path_off = -1; out->path_len = 0; out->n_scores = 0; out->work = 0;
         }
         return;
     }
-    const ull* __restrict__ seg = A.seg;
     const int64_t* __restrict__ seg_off = A.seg_off;
     const int32_t* __restrict__ out_off = A.out_off;
     const int32_t* __restrict__ out_dst = A.out_dst;
-    const ull* __restrict__ rd = A.rd;
-
-    ull* dir = reinterpret_cast<ull*>(arena + A.o_dir);
-    Page* pages = reinterpret_cast<Page*>(arena + A.o_pages);
-    ull* mkey = reinterpret_cast<ull*>(arena + A.o_mkey);
-    int32_t* mval = reinterpret_cast<int32_t*>(arena + A.o_mval);
-    int32_t* Tv = reinterpret_cast<int32_t*>(arena + A.o_tv);
-    int32_t* Tt = reinterpret_cast<int32_t*>(arena + A.o_tt);
-    Lists L[2];
-    {
-        int32_t* base = reinterpret_cast<int32_t*>(arena + A.o_lists);
-        const int64_t c = A.list_cap;
-        for (int j = 0; j < 2; ++j) {
-            int32_t* p = base + (int64_t)j * 6 * c;
-            L[j].v = p; L[j].k = p + c; L[j].o = p + 2 * c; L[j].w = p + 3 * c; L[j].t = p + 4 * c; L[j].d = p + 5 * c;
-        }
-    }
+    q.dir = reinterpret_cast<ull*>(arena + A.o_dir);
+    q.pages = reinterpret_cast<Page*>(arena + A.o_pages);
+    q.mkey = reinterpret_cast<ull*>(arena + A.o_mkey);
+    q.Tv = reinterpret_cast<int32_t*>(arena + A.o_tv);
+    q.Tt = reinterpret_cast<int32_t*>(arena + A.o_tt);
+    q.tb = A.traceback != 0;
+    q.prune = A.prune != GWFA_PRUNE_NONE;
+    uint32_t* hdr = reinterpret_cast<uint32_t*>(arena + A.o_hdr);
+    int32_t* const lbase = reinterpret_cast<int32_t*>(arena + A.o_lists);
+    const int64_t lcap = A.list_cap;
+    // list j (0 or 1): six SoA arrays of list_cap entries
+    auto LL = [&](int j) -> Lists {
+        int32_t* p = lbase + (int64_t)j * 9 * lcap;
+        Lists x;
+        x.v = p; x.k = p + lcap; x.o = p + 2 * lcap; x.w = p + 3 * lcap; x.t = p + 4 * lcap; x.d = p + 5 * lcap;
+        x.l = p + 6 * lcap;
+        x.b = reinterpret_cast<int64_t*>(p + 7 * lcap);
+        return x;
+    };
     int32_t* cbase = reinterpret_cast<int32_t*>(arena + A.o_cand);
     const int64_t cc = A.cand_cap;
-    int32_t *cu = cbase, *ck = cbase + cc, *cW = cbase + 2 * cc, *ct = cbase + 3 * cc, *cd = cbase + 4 * cc;
+    int32_t *cu = cbase, *ck = cbase + cc, *cW = cbase + 2 * cc, *ct = cbase + 3 * cc;
+    ull* gkeys = reinterpret_cast<ull*>(arena + A.o_sort);
+    int32_t* gidx = reinterpret_cast<int32_t*>(gkeys + A.sort_cap);
 
-    const bool tb = A.traceback != 0;
-    // initial directory size: dir_factor slots per 32 query bases
     int cap_log2 = 8;
     {
-        const int64_t want = ((int64_t)qlen / 32 + 1) * A.dir_factor;
+        const int64_t want = ((int64_t)q.qlen / 32 + 1) * A.dir_factor;
         while (cap_log2 < A.dir_log2_max && ((int64_t)1 << cap_log2) < want) ++cap_log2;
     }
     int status = -1;
-    int32_t s = 0, b = 0;
+    int32_t s = 0;
+    int cur = 1;
+    int32_t n_cur = 0;
     int64_t work = 0;
-    for (;;) {  // attempts with growing directory
+    uint32_t chunks = 0;
+    for (;;) {   // attempts with a growing directory
         const uint32_t mask = (1u << cap_log2) - 1;
-        const int32_t tcap = (int32_t)((mask + 1) >> 1);
+        const int32_t half = (int32_t)((mask + 1) >> 1);
+        q.mask = mask;
         for (uint32_t i = tid; i <= mask; i += BLOCK) {
-            dir[i] = 0;
-            if (tb) mkey[i] = 0;
+            q.dir[i] = 0;
+            if (q.tb) q.mkey[i] = 0;
         }
         if (tid == 0) {
-            S.n[0] = S.n[1] = 0; S.ncand = 0; S.dirn = 0; S.tn = 0; S.flags = 0;
+            const uint32_t g = hdr[0] + 1;
+            hdr[0] = g;
+            S.gen = g;
+            S.n_out = 0; S.ncand = 0; S.dirn = 0; S.mn = 0; S.flags = 0;
             S.chunks = 0; S.cross = 0; S.adm = 0; S.mlp = 0; S.dropped = 0;
+            S.found = 0; S.endkey = ~0ull; S.amax = 0; S.imax = 0;
+            S.tick[0] = S.tick[1] = S.tick[2] = S.tick[3] = 0;
         }
         __syncthreads();
-        if (tid == 0) {
-            bool ins;
-            const int ds = dir_insert(dir, mask, dkey(vs, 0), ins);
-            page_init(&pages[ds]);
-            L[0].v[0] = vs; L[0].k[0] = 0; L[0].o[0] = 0; L[0].w[0] = 0; L[0].t[0] = 0; L[0].d[0] = ds;
-            S.n[0] = 1; S.dirn = 1;
-            if (tb) { Tv[0] = vs; Tt[0] = -1; S.tn = 1; }   // Algorithm 5 on the start vertex
+        q.gen = S.gen;
+        if (tid == 0) {   // score 0 starts from the start diagonal (v_s, 0) at offset 0
+            const int ds = dir_insert(q.dir, mask, dkey(q.vs, 0), &S.dirn);
+            const int32_t t0 = q.tb ? trace_push(q, S, q.vs, -1) : -1;
+            const Lists L0 = LL(0);
+            L0.v[0] = q.vs; L0.k[0] = 0; L0.o[0] = 0; L0.w[0] = 0; L0.t[0] = t0; L0.d[0] = ds;
+            L0.b[0] = seg_off[q.vs];
+            L0.l[0] = (int32_t)(seg_off[q.vs + 1] - seg_off[q.vs]);
+            S.n_out = 1;
         }
         __syncthreads();
-        b = 0; s = 0; work = 0; status = -1;
-        bool restart = false;
+        cur = 1;
+        n_cur = 0;
+        s = 0;
+        work = 0;
+        status = -1;
         int rflags = 0;
+        chunks = 0;
         for (;; ++s) {
-            // ================= EXTEND (Algorithm 2) =================
-            if (tid == 0) { S.found = 0; S.endkey = ~0ull; S.amax = 0; S.ncand = 0; }
-            __syncthreads();
-            int32_t lo = 0, hi = S.n[b];
-            uint32_t chunks = 0;
-            for (int round = 0;; ++round) {
-                if (round > 0) {
-                    // crossing targets admitted last round: take (W, t) from
-                    // the slot, where every crossing predecessor of this
-                    // round left its max (Algorithm 5 pushes (u, t)).
-                    for (int32_t idx = lo + tid; idx < hi; idx += BLOCK) {
-                        const int32_t ds = L[b].d[idx], k = L[b].k[idx];
-                        const ull x = pages[ds].wt[k & 31];
-                        L[b].w[idx] = wt_W(x);
-                        const int32_t tp = wt_t(x);
-                        L[b].t[idx] = tp;
-                        if (tb) {
-                            const int32_t v = L[b].v[idx];
-                            bool ins;
-                            const int ms = dir_insert(mkey, mask, dkey(v, tp), ins);
-                            if (ms < 0) {
-                                atomicOr(&S.flags, F_GROW);
-                            } else if (ins) {
-                                const int ti = atomicAdd(&S.tn, 1);
-                                if (ti < tcap) { Tv[ti] = v; Tt[ti] = tp; mval[ms] = ti; }
-                                else atomicOr(&S.flags, F_GROW);
+            const int nb = 1 - cur;
+            const Lists Ld = LL(nb);
+            int32_t n1 = 0;           // diagonals produced by the expansion
+            ull tk = wall_clock64();
+            if (s > 0) {
+                if (tid == 0) { S.found = 0; S.endkey = ~0ull; S.amax = 0; S.imax = 0; }
+                __syncthreads();
+                // ========== EXPAND (Algorithm 3) + EXTEND of what it admits ==========
+                const Lists Ls = LL(cur);
+                const int32_t n = n_cur;
+                int32_t outbase = 0;
+                int adm = 0;
+                for (int32_t base = 0; base < n; base += BLOCK) {
+                    const int32_t idx = base + tid;
+                    // three fixed output slots: diagonals k-1, k, k+1
+                    bool ov0 = false, ov1 = false, ov2 = false;
+                    int32_t oo0 = 0, ow0 = 0, ot0 = 0, od0 = -1; bool on0 = false;
+                    int32_t oo1 = 0, ow1 = 0, ot1 = 0, od1 = -1;
+                    int32_t oo2 = 0, ow2 = 0, ot2 = 0, od2 = -1; bool on2 = false;
+                    int32_t v = 0, k = 0, Lv = 0;
+                    int64_t sb = 0;
+                    if (idx < n) {
+                        v = Ls.v[idx];
+                        k = Ls.k[idx];
+                        const int32_t o0 = Ls.o[idx], W0 = Ls.w[idx], t0 = Ls.t[idx], ds0 = Ls.d[idx];
+                        sb = Ls.b[idx];
+                        Lv = Ls.l[idx];
+                        const int32_t i0 = k + o0;
+                        // neighbours k-2, k-1, k+1, k+2 of the same vertex are
+                        // adjacent in the sorted list
+                        bool pm1 = false, pm2 = false, pp1 = false, pp2 = false;
+                        int32_t o1 = 0, W1 = 0, t1 = 0, d1 = -1, o2 = 0, W2 = 0, t2 = 0;
+                        if (idx >= 1 && Ls.v[idx - 1] == v) {
+                            const int32_t ka = Ls.k[idx - 1];
+                            if (ka == k - 1) {
+                                pm1 = true;
+                                pm2 = idx >= 2 && Ls.v[idx - 2] == v && Ls.k[idx - 2] == k - 2;
+                            } else {
+                                pm2 = ka == k - 2;
+                            }
+                        }
+                        if (idx + 1 < n && Ls.v[idx + 1] == v) {
+                            const int32_t kc = Ls.k[idx + 1];
+                            if (kc == k + 1) {
+                                pp1 = true;
+                                o1 = Ls.o[idx + 1]; W1 = Ls.w[idx + 1]; t1 = Ls.t[idx + 1]; d1 = Ls.d[idx + 1];
+                                if (idx + 2 < n && Ls.v[idx + 2] == v && Ls.k[idx + 2] == k + 2) {
+                                    pp2 = true;
+                                    o2 = Ls.o[idx + 2]; W2 = Ls.w[idx + 2]; t2 = Ls.t[idx + 2];
+                                }
+                            } else if (kc == k + 2) {
+                                pp2 = true;
+                                o2 = Ls.o[idx + 1]; W2 = Ls.w[idx + 1]; t2 = Ls.t[idx + 1];
+                            }
+                        }
+                        const int sl = k & 31;
+                        const int32_t kp0 = k >> 5;
+                        // output k-1 (this source owns it when k-1 and k-2 are absent): deletion
+                        if (!pm1 && !pm2 && o0 < Lv) {
+                            const int pg = (sl > 0) ? ds0 : dir_find(q.dir, mask, dkey(v, kp0 - 1));
+                            bool rec = false;
+                            int32_t rv = 0;
+                            if (pg >= 0) {
+                                const ull w = q.pages[pg].R[(k - 1) & 31];
+                                rec = rgen(w) == q.gen;
+                                rv = rval(w);
+                            }
+                            if (!rec || o0 + 1 > rv) {
+                                ov0 = true; oo0 = o0 + 1; ow0 = W0 + 1; ot0 = t0; od0 = pg; on0 = !rec;
+                            }
+                        }
+                        // output k (owned when k-1 is absent): mismatch, deletion from k+1
+                        if (!pm1) {
+                            int32_t bo = -1, bw = -1, bt = -1;
+                            if (i0 < q.qlen && o0 < Lv) { bo = o0 + 1; bw = W0 + 1; bt = t0; }
+                            if (pp1 && o1 < Lv && (o1 + 1 > bo || (o1 + 1 == bo && W1 + 1 > bw))) {
+                                bo = o1 + 1; bw = W1 + 1; bt = t1;
+                            }
+                            if (bo > o0) { ov1 = true; oo1 = bo; ow1 = bw; ot1 = bt; od1 = ds0; }
+                        }
+                        // output k+1 (always owned): insertion, mismatch at k+1, deletion from k+2
+                        {
+                            int32_t bo = -1, bw = -1, bt = -1;
+                            if (i0 < q.qlen) { bo = o0; bw = W0; bt = t0; }
+                            if (pp1 && k + 1 + o1 < q.qlen && o1 < Lv && (o1 + 1 > bo || (o1 + 1 == bo && W1 + 1 > bw))) {
+                                bo = o1 + 1; bw = W1 + 1; bt = t1;
+                            }
+                            if (pp2 && o2 < Lv && (o2 + 1 > bo || (o2 + 1 == bo && W2 + 1 > bw))) {
+                                bo = o2 + 1; bw = W2 + 1; bt = t2;
+                            }
+                            if (bo >= 0) {
+                                if (pp1) {
+                                    if (bo > o1) { ov2 = true; oo2 = bo; ow2 = bw; ot2 = bt; od2 = d1; on2 = false; }
+                                } else {
+                                    const int pg = (sl < 31) ? ds0 : dir_find(q.dir, mask, dkey(v, kp0 + 1));
+                                    bool rec = false;
+                                    int32_t rv = 0;
+                                    if (pg >= 0) {
+                                        const ull w = q.pages[pg].R[(k + 1) & 31];
+                                        rec = rgen(w) == q.gen;
+                                        rv = rval(w);
+                                    }
+                                    if (!rec || bo > rv) { ov2 = true; oo2 = bo; ow2 = bw; ot2 = bt; od2 = pg; on2 = !rec; }
+                                }
                             }
                         }
                     }
-                    if (tb) {
-                        const int f = read_uniform(S.flags);
-                        if (f) { rflags = f; restart = true; break; }
-                        for (int32_t idx = lo + tid; idx < hi; idx += BLOCK) {
-                            const int ms = dir_find(mkey, mask, dkey(L[b].v[idx], L[b].t[idx]));
-                            L[b].t[idx] = ms >= 0 ? mval[ms] : -1;
+                    // extension of the admitted outputs: the first 32-base
+                    // window of all three is fetched before any is used
+                    int32_t lx0 = 0, lx1 = 0, lx2 = 0;
+                    {
+                        const int32_t i0 = k - 1 + oo0, i1 = k + oo1, i2 = k + 1 + oo2;
+                        const int32_t m0 = ov0 ? min(q.qlen - i0, Lv - oo0) : 0;
+                        const int32_t m1 = ov1 ? min(q.qlen - i1, Lv - oo1) : 0;
+                        const int32_t m2 = ov2 ? min(q.qlen - i2, Lv - oo2) : 0;
+                        const ull x0 = (m0 > 0) ? (win32(q.rd, q.q0 + i0) ^ win32(A.seg, sb + oo0)) : 0ull;
+                        const ull x1 = (m1 > 0) ? (win32(q.rd, q.q0 + i1) ^ win32(A.seg, sb + oo1)) : 0ull;
+                        const ull x2 = (m2 > 0) ? (win32(q.rd, q.q0 + i2) ^ win32(A.seg, sb + oo2)) : 0ull;
+                        chunks += (m0 > 0) + (m1 > 0) + (m2 > 0);
+                        lx0 = x0 ? min((int32_t)(__clzll((long long)x0) >> 1), m0) : min(32, m0);
+                        lx1 = x1 ? min((int32_t)(__clzll((long long)x1) >> 1), m1) : min(32, m1);
+                        lx2 = x2 ? min((int32_t)(__clzll((long long)x2) >> 1), m2) : min(32, m2);
+                        // whole windows matched and bases remain: continue
+                        if (lx0 == 32 && m0 > 32) lx0 = 32 + lcp(q.rd, q.q0 + i0 + 32, A.seg, sb + oo0 + 32, m0 - 32, chunks);
+                        if (lx1 == 32 && m1 > 32) lx1 = 32 + lcp(q.rd, q.q0 + i1 + 32, A.seg, sb + oo1 + 32, m1 - 32, chunks);
+                        if (lx2 == 32 && m2 > 32) lx2 = 32 + lcp(q.rd, q.q0 + i2 + 32, A.seg, sb + oo2 + 32, m2 - 32, chunks);
+                    }
+                    const int cnt = (int)ov0 + (int)ov1 + (int)ov2;
+                    int total;
+                    const int pos = block_excl_scan<BLOCK>(cnt, total, S.scan);
+                    adm += cnt;
+                    int slot = 0;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const bool vj = (j == 0) ? ov0 : ((j == 1) ? ov1 : ov2);
+                        int ncr = 0;
+                        int32_t e0 = 0, k2 = 0, Wj = 0, tj = 0;
+                        if (vj) {
+                            const int32_t kj = k - 1 + j;
+                            const int32_t lj = (j == 0) ? lx0 : ((j == 1) ? lx1 : lx2);
+                            int32_t o = ((j == 0) ? oo0 : ((j == 1) ? oo1 : oo2)) + lj;
+                            Wj = ((j == 0) ? ow0 : ((j == 1) ? ow1 : ow2)) + lj;
+                            tj = (j == 0) ? ot0 : ((j == 1) ? ot1 : ot2);
+                            int d = (j == 0) ? od0 : ((j == 1) ? od1 : od2);
+                            const bool nw = (j == 0) ? on0 : ((j == 1) ? false : on2);
+                            const int32_t p = outbase + pos + slot;
+                            ++slot;
+                            if (d < 0) d = dir_insert(q.dir, mask, dkey(v, kj >> 5), &S.dirn);
+                            if (p >= A.list_cap) {
+                                atomicOr(&S.flags, F_LIST);
+                            } else if (d < 0) {
+                                atomicOr(&S.flags, F_GROW);
+                            } else {
+                                ncr = record_entry(A, q, S, v, kj, o, Wj, d, nw, Lv);
+                                Ld.v[p] = v; Ld.k[p] = kj; Ld.o[p] = o; Ld.w[p] = Wj; Ld.t[p] = tj; Ld.d[p] = d;
+                                Ld.l[p] = Lv; Ld.b[p] = sb;
+                                e0 = out_off[v];
+                                k2 = kj + Lv;
+                            }
+                        }
+                        const int cp = wave_alloc(ncr, &S.ncand);
+                        for (int e = 0; e < ncr; ++e) {
+                            const int c = cp + e;
+                            if (c < A.cand_cap) {
+                                cu[c] = out_dst[e0 + e]; ck[c] = k2; cW[c] = Wj; ct[c] = tj;
+                            } else {
+                                atomicOr(&S.flags, F_LIST);
+                            }
                         }
                     }
+                    outbase += total;
                 }
-                for (int32_t base = lo; base < hi; base += BLOCK) {
+                n1 = min(outbase, A.list_cap);
+                if (adm) atomicAdd(&S.adm, (ull)adm);
+                if (tid == 0) S.n_out = n1;
+            }
+            if (tid == 0) { const ull t2 = wall_clock64(); S.tick[0] += t2 - tk; tk = t2; }
+            // ========== crossings (Algorithm 2, same score, cost 0), in rounds ==========
+            int32_t xlo = n1, xhi = (s == 0) ? 1 : n1;
+            const int32_t preset_hi = (s == 0) ? 1 : 0;   // the start entry has its W and t
+            bool restart = false;
+            for (int round = 0;; ++round) {
+                // (1) extend the diagonals created by the previous round
+                for (int32_t base = xlo; base < xhi; base += BLOCK) {
                     const int32_t idx = base + tid;
-                    int ncand = 0;
-                    int32_t e0 = 0, k = 0, Lv = 0, W = 0, t = 0;
-                    if (idx < hi) {
-                        const int32_t v = L[b].v[idx];
-                        k = L[b].k[idx];
-                        int32_t o = L[b].o[idx];
-                        W = L[b].w[idx];
-                        t = L[b].t[idx];
-                        const int32_t ds = L[b].d[idx];
-                        const int64_t sb = seg_off[v];
-                        Lv = (int32_t)(seg_off[v + 1] - sb);
-                        int32_t i = k + o;
-                        const int32_t lim = min(qlen - i, Lv - o);
-                        const int32_t l = lcp(rd, q0 + i, seg, sb + o, lim, chunks);
-                        o += l; W += l; i += l;
-                        Page* pg = &pages[ds];
-                        const int sl = k & 31;
-                        pg->off[sl] = o;
-                        pg->stamp[sl] = s;
-                        pg->wt[sl] = pack_wt(W, t);
-                        L[b].o[idx] = o;
-                        L[b].w[idx] = W;
-                        if (i == qlen) {
-                            S.found = 1;
-                            if (o >= 1 || v == vs) atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
+                    int ncr = 0;
+                    int32_t e0 = 0, k2 = 0, W = 0, t = 0;
+                    if (idx < xhi) {
+                        const int32_t v = Ld.v[idx], k = Ld.k[idx], d = Ld.d[idx];
+                        int32_t o = Ld.o[idx];
+                        W = Ld.w[idx];
+                        t = Ld.t[idx];
+                        if (idx >= preset_hi) {
+                            if (q.prune) W = rval(q.pages[d].Wc[k & 31]);
+                            t = q.tb ? trace_push(q, S, v, t) : -1;
                         }
-                        if (A.prune == GWFA_PRUNE_HEURISTIC || A.prune == GWFA_PRUNE_LEARNED) atomicMax(&S.amax, i + W);
-                        if (o == Lv) { e0 = out_off[v]; ncand = out_off[v + 1] - e0; }
+                        const int64_t sb = seg_off[v];
+                        const int32_t Lv = (int32_t)(seg_off[v + 1] - sb);
+                        ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, chunks);
+                        Ld.o[idx] = o; Ld.w[idx] = W; Ld.t[idx] = t; Ld.l[idx] = Lv; Ld.b[idx] = sb;
+                        e0 = out_off[v];
+                        k2 = k + Lv;
                     }
-                    const int pos = wave_alloc(ncand, &S.ncand);
-                    for (int e = 0; e < ncand; ++e) {
-                        const int c = pos + e;
+                    const int cp = wave_alloc(ncr, &S.ncand);
+                    for (int e = 0; e < ncr; ++e) {
+                        const int c = cp + e;
                         if (c < A.cand_cap) {
-                            cu[c] = out_dst[e0 + e]; ck[c] = k + Lv; cW[c] = W; ct[c] = t;
+                            cu[c] = out_dst[e0 + e]; ck[c] = k2; cW[c] = W; ct[c] = t;
                         } else {
                             atomicOr(&S.flags, F_LIST);
                         }
@@ -338,246 +632,185 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 }
                 __syncthreads();
                 const int32_t nc = S.ncand;
-                {
-                    const int f = read_uniform(S.flags);
-                    if (f) { rflags = f; restart = true; break; }
-                }
-                if (nc == 0) break;
-                // (a) pages for the crossing targets
-                for (int32_t c = tid; c < nc; c += BLOCK) {
-                    bool ins;
-                    const int ds = dir_insert(dir, mask, dkey(cu[c], ck[c] >> 5), ins);
-                    if (ds < 0) atomicOr(&S.flags, F_GROW);
-                    else if (ins) { page_init(&pages[ds]); atomicAdd(&S.dirn, 1); }
-                    cd[c] = ds;
-                }
-                {
-                    const int f = read_uniform(S.flags);
-                    if (f) { rflags = f; restart = true; break; }
-                }
+                const int f1 = S.flags | ((S.dirn > half || S.mn > half) ? F_GROW : 0);
+                __syncthreads();
                 if (tid == 0) S.ncand = 0;
-                // (b) claim never-seen diagonals; every predecessor of this
-                // round folds its (W, t) into the slot with a max
+                if (f1) { rflags = f1; restart = true; break; }
+                if (nc == 0) break;
+                // (2) claim never-seen diagonals (no record of this query); every
+                // predecessor of this round folds its W into the slot with a max
+                const ull mine = mkR(q.gen, CLAIM_BASE + round);
                 for (int32_t base = 0; base < nc; base += BLOCK) {
                     const int32_t c = base + tid;
                     int claim = 0;
+                    int ds = -1;
                     if (c < nc) {
-                        const int ds = cd[c];
-                        Page* pg = &pages[ds];
-                        const int sl = ck[c] & 31;
-                        const int32_t st = __hip_atomic_load(&pg->stamp[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        bool part = false;
-                        if (st == ST_EMPTY) {
-                            const int32_t old = atomicCAS(&pg->stamp[sl], ST_EMPTY, ST_CLAIM);
-                            if (old == ST_EMPTY) { claim = 1; part = true; }
-                            else if (old == ST_CLAIM) part = true;
-                        } else if (st == ST_CLAIM) {
-                            part = true;
+                        ds = dir_insert(q.dir, mask, dkey(cu[c], ck[c] >> 5), &S.dirn);
+                        if (ds < 0) {
+                            atomicOr(&S.flags, F_GROW);
+                        } else {
+                            ull* rp = &q.pages[ds].R[ck[c] & 31];
+                            const ull w = __hip_atomic_load(rp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            bool part = false;
+                            if (rgen(w) != q.gen) {
+                                const ull old = atomicCAS(rp, w, mine);
+                                if (old == w) { claim = 1; part = true; }
+                                else if (old == mine) part = true;
+                            } else if (w == mine) {
+                                part = true;
+                            }
+                            if (part && q.prune) atomicMax(&q.pages[ds].Wc[ck[c] & 31], mkR(q.gen, cW[c]));
                         }
-                        if (part) atomicMax(&pg->wt[sl], pack_wt(cW[c], ct[c]));
                     }
-                    const int pos = wave_alloc(claim, &S.n[b]);
+                    const int pos = wave_alloc(claim, &S.n_out);
                     if (claim) {
                         if (pos < A.list_cap) {
-                            L[b].v[pos] = cu[c]; L[b].k[pos] = ck[c]; L[b].o[pos] = 0;
-                            L[b].w[pos] = 0; L[b].t[pos] = -1; L[b].d[pos] = cd[c];
+                            Ld.v[pos] = cu[c]; Ld.k[pos] = ck[c]; Ld.o[pos] = 0; Ld.w[pos] = cW[c]; Ld.t[pos] = ct[c];
+                            Ld.d[pos] = ds;
                         } else {
                             atomicOr(&S.flags, F_LIST);
                         }
                     }
                 }
                 __syncthreads();
-                const int32_t hi_next = S.n[b];
-                {
-                    const int f = read_uniform(S.flags);
-                    if (f) { rflags = f; restart = true; break; }
-                }
-                lo = hi;
-                hi = hi_next;
-                if (tid == 0) S.cross += (ull)(hi - lo);
+                const int32_t xn = S.n_out;
+                const int f2 = S.flags | ((S.dirn > half) ? F_GROW : 0);
+                __syncthreads();
+                if (f2) { rflags = f2; restart = true; break; }
+                xlo = xhi;
+                xhi = xn;
+                if (tid == 0) S.cross += (ull)(xhi - xlo);
             }
             if (restart) break;
-            if (chunks) atomicAdd(&S.chunks, (ull)chunks);
-            const int32_t n = S.n[b];
-            work += n;
-            // ================= END TEST =================
-            if (S.found) { status = GWFA_ST_OK; break; }
+            if (tid == 0) { const ull t2 = wall_clock64(); S.tick[1] += t2 - tk; tk = t2; }
+            const int32_t ntot = xhi;
+            work += ntot;
+            __syncthreads();
+            const int found = S.found;
+            const int32_t amax = S.amax;
+            __syncthreads();
+            // ========== end test (extension mode) ==========
+            if (found) {
+                status = GWFA_ST_OK;
+                if (q.tb) {
+                    if (tid == 0) S.tend = -1;
+                    __syncthreads();
+                    const int32_t ev = (int32_t)(S.endkey >> 32), eo = (int32_t)(S.endkey & 0xffffffffull);
+                    for (int32_t idx = tid; idx < ntot; idx += BLOCK)
+                        if (Ld.v[idx] == ev && Ld.o[idx] == eo && Ld.k[idx] + eo == q.qlen) S.tend = Ld.t[idx];
+                    __syncthreads();
+                }
+                break;
+            }
             if (A.max_score >= 0 && s >= A.max_score) { status = GWFA_ST_MAX_SCORE; break; }
             // cannot happen for valid input (the query can always be
             // inserted); a guard so that every workgroup finishes
-            if (n == 0 || s > qlen + 1) { status = GWFA_ST_MAX_SCORE; break; }
-            int32_t ncur = n;
-            // ================= PRUNE (Algorithm 4) =================
-            if (A.prune == GWFA_PRUNE_HEURISTIC && S.amax > A.a_diff) {
-                const int nb = 1 - b;
-                const int32_t amax = S.amax;
+            if (ntot == 0 || s > q.qlen + 1) { status = GWFA_ST_MAX_SCORE; break; }
+            // ========== merge the crossing diagonals into the sorted list ==========
+            const int32_t m = ntot - n1;
+            if (m > 0) {
+                int N = 1;
+                while (N < m) N <<= 1;
+                ull* keys = (N <= XS_LDS) ? S.skeys : gkeys;
+                int32_t* sidx = (N <= XS_LDS) ? S.sidx : gidx;
+                if (N > A.sort_cap) { rflags = F_LIST; break; }
+                if (m <= 64) {
+                    // small set: each key's rank is the number of smaller keys
+                    for (int i = tid; i < m; i += BLOCK) S.skeys[i] = skey(Ld.v[n1 + i], Ld.k[n1 + i]);
+                    __syncthreads();
+                    for (int i = tid; i < m; i += BLOCK) {
+                        const ull ki = S.skeys[i];
+                        int32_t rk = 0;
+                        for (int j = 0; j < m; ++j) rk += S.skeys[j] < ki;
+                        S.skeys2[rk] = ki;
+                        S.sidx[rk] = n1 + i;
+                    }
+                    __syncthreads();
+                    keys = S.skeys2;
+                    sidx = S.sidx;
+                    N = m;
+                } else {
+                    for (int i = tid; i < N; i += BLOCK) {
+                        keys[i] = (i < m) ? skey(Ld.v[n1 + i], Ld.k[n1 + i]) : ~0ull;
+                        sidx[i] = n1 + i;
+                    }
+                    __syncthreads();
+                    bitonic<BLOCK>(keys, sidx, N);
+                }
+                const Lists Lm = LL(cur);
+                if (N <= XS_LDS) {
+                    // main entry j lands at j + (crossing keys below it); crossing
+                    // entry x at x + (main keys below it), which is the first j
+                    // whose rank exceeds x (ranks do not decrease along the list)
+                    for (int32_t j = tid; j < n1; j += BLOCK) {
+                        const int32_t rj = lower_bound_keys(keys, m, skey(Ld.v[j], Ld.k[j]));
+                        const int32_t rp = (j == 0) ? 0 : lower_bound_keys(keys, m, skey(Ld.v[j - 1], Ld.k[j - 1]));
+                        for (int32_t x = rp; x < rj; ++x) S.xcnt[x] = j;
+                        if (j == n1 - 1)
+                            for (int32_t x = rj; x < m; ++x) S.xcnt[x] = n1;
+                        copy_entry(Ld, j, Lm, j + rj);
+                    }
+                    if (n1 == 0)
+                        for (int32_t x = tid; x < m; x += BLOCK) S.xcnt[x] = 0;
+                    __syncthreads();
+                    for (int32_t x = tid; x < m; x += BLOCK) copy_entry(Ld, sidx[x], Lm, x + S.xcnt[x]);
+                } else {
+                    for (int32_t j = tid; j < n1; j += BLOCK)
+                        copy_entry(Ld, j, Lm, j + lower_bound_keys(keys, m, skey(Ld.v[j], Ld.k[j])));
+                    for (int32_t x = tid; x < m; x += BLOCK)
+                        copy_entry(Ld, sidx[x], Lm, x + lower_bound_list(Ld, n1, keys[x]));
+                }
                 __syncthreads();
-                if (tid == 0) S.n[nb] = 0;
-                __syncthreads();
-                for (int32_t base = 0; base < ncur; base += BLOCK) {
+            } else {
+                cur = nb;
+            }
+            if (tid == 0) { const ull t2 = wall_clock64(); S.tick[2] += t2 - tk; tk = t2; }
+            n_cur = ntot;
+            // ========== pruning (Algorithm 4) ==========
+            if (A.prune == GWFA_PRUNE_HEURISTIC && amax > A.a_diff) {
+                const Lists Ls = LL(cur);
+                const Lists Lp = LL(1 - cur);
+                int32_t outbase = 0;
+                int dropped = 0;
+                for (int32_t base = 0; base < n_cur; base += BLOCK) {
                     const int32_t idx = base + tid;
                     int keep = 0;
-                    if (idx < ncur) {
-                        const int32_t a = L[b].k[idx] + L[b].o[idx] + L[b].w[idx];
+                    if (idx < n_cur) {
+                        const int32_t a = Ls.k[idx] + Ls.o[idx] + Ls.w[idx];
                         keep = (amax - a < A.a_diff) ? 1 : 0;
-                        if (!keep) {
-                            const int32_t ds = L[b].d[idx], k = L[b].k[idx];
-                            pages[ds].stamp[k & 31] = s | ST_PRUNED;   // record kept, not in F_s
+                        if (!keep) {   // the diagonal keeps its offset as its record
+                            q.pages[Ls.d[idx]].R[Ls.k[idx] & 31] = mkR(q.gen, Ls.o[idx]);
+                            ++dropped;
                         }
                     }
-                    const int pos = wave_alloc(keep, &S.n[nb]);
-                    if (keep) {
-                        L[nb].v[pos] = L[b].v[idx]; L[nb].k[pos] = L[b].k[idx]; L[nb].o[pos] = L[b].o[idx];
-                        L[nb].w[pos] = L[b].w[idx]; L[nb].t[pos] = L[b].t[idx]; L[nb].d[pos] = L[b].d[idx];
-                    }
+                    int total;
+                    const int pos = block_excl_scan<BLOCK>(keep, total, S.scan);
+                    if (keep) copy_entry(Ls, idx, Lp, outbase + pos);
+                    outbase += total;
                 }
+                if (dropped) atomicAdd(&S.dropped, dropped);
+                cur = 1 - cur;
+                n_cur = outbase;
                 __syncthreads();
-                if (tid == 0) S.dropped += ncur - S.n[nb];
-                b = nb;
-                ncur = S.n[b];
-            }
-            // ================= EXPAND (Algorithm 3) =================
-            {
-                const int nb = 1 - b;
-                __syncthreads();
-                if (tid == 0) S.n[nb] = 0;
-                __syncthreads();
-                int adm = 0;
-                for (int32_t base = 0; base < ncur; base += BLOCK) {
-                    const int32_t idx = base + tid;
-                    int cnt = 0;
-                    int32_t ok[3], oo[3], ow[3], ot[3], od[3];
-                    int32_t v = 0;
-                    if (idx < ncur) {
-                        v = L[b].v[idx];
-                        const int32_t k = L[b].k[idx], o0 = L[b].o[idx], W0 = L[b].w[idx], t0 = L[b].t[idx];
-                        const int32_t ds0 = L[b].d[idx];
-                        const int32_t Lv = (int32_t)(seg_off[v + 1] - seg_off[v]);
-                        const int32_t i0 = k + o0;
-                        const int sl = k & 31;
-                        const int32_t kp0 = k >> 5;
-                        const int pl = (sl < 2) ? dir_find(dir, mask, dkey(v, kp0 - 1)) : -1;
-                        const int ph = (sl > 29) ? dir_find(dir, mask, dkey(v, kp0 + 1)) : -1;
-                        // neighbours d = -2, -1, +1, +2 -> j = 0, 1, 2, 3
-                        int32_t nst[4], nof[4], npg[4];
-                        ull nwt[4];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int d = (j < 2) ? (j - 2) : (j - 1);
-                            const int x = sl + d;
-                            const int p = (x < 0) ? pl : ((x > 31) ? ph : ds0);
-                            npg[j] = p;
-                            if (p >= 0) {
-                                const int xs = x & 31;
-                                nst[j] = pages[p].stamp[xs];
-                                nof[j] = pages[p].off[xs];
-                                nwt[j] = (j >= 2 && nst[j] == s) ? pages[p].wt[xs] : 0ull;
-                            } else {
-                                nst[j] = ST_EMPTY; nof[j] = 0; nwt[j] = 0ull;
-                            }
-                        }
-                        const bool pm2 = nst[0] == s, pm1 = nst[1] == s, pp1 = nst[2] == s, pp2 = nst[3] == s;
-                        // output k+1: insertion from k, mismatch at k+1, deletion from k+2
-                        {
-                            int32_t bo = -1, bw = -1, bt = -1;
-                            if (i0 < qlen) { bo = o0; bw = W0; bt = t0; }
-                            if (pp1) {
-                                const int32_t o1 = nof[2];
-                                if (k + 1 + o1 < qlen && o1 < Lv) {
-                                    const int32_t w1 = wt_W(nwt[2]) + 1;
-                                    if (o1 + 1 > bo || (o1 + 1 == bo && w1 > bw)) { bo = o1 + 1; bw = w1; bt = wt_t(nwt[2]); }
-                                }
-                            }
-                            if (pp2) {
-                                const int32_t o2 = nof[3];
-                                if (o2 < Lv) {
-                                    const int32_t w2 = wt_W(nwt[3]) + 1;
-                                    if (o2 + 1 > bo || (o2 + 1 == bo && w2 > bw)) { bo = o2 + 1; bw = w2; bt = wt_t(nwt[3]); }
-                                }
-                            }
-                            const bool rec = nst[2] != ST_EMPTY;
-                            if (bo >= 0 && (!rec || bo > nof[2])) {
-                                ok[cnt] = k + 1; oo[cnt] = bo; ow[cnt] = bw; ot[cnt] = bt; od[cnt] = npg[2]; ++cnt;
-                            }
-                        }
-                        // output k (owned when k-1 is absent): mismatch at k, deletion from k+1
-                        if (!pm1) {
-                            int32_t bo = -1, bw = -1, bt = -1;
-                            if (i0 < qlen && o0 < Lv) { bo = o0 + 1; bw = W0 + 1; bt = t0; }
-                            if (pp1 && nof[2] < Lv) {
-                                const int32_t o1 = nof[2] + 1, w1 = wt_W(nwt[2]) + 1;
-                                if (o1 > bo || (o1 == bo && w1 > bw)) { bo = o1; bw = w1; bt = wt_t(nwt[2]); }
-                            }
-                            if (bo > o0) { ok[cnt] = k; oo[cnt] = bo; ow[cnt] = bw; ot[cnt] = bt; od[cnt] = ds0; ++cnt; }
-                        }
-                        // output k-1 (owned when k-1 and k-2 are absent): deletion from k
-                        if (!pm1 && !pm2 && o0 < Lv) {
-                            const bool rec = nst[1] != ST_EMPTY;
-                            if (!rec || o0 + 1 > nof[1]) {
-                                ok[cnt] = k - 1; oo[cnt] = o0 + 1; ow[cnt] = W0 + 1; ot[cnt] = t0; od[cnt] = npg[1]; ++cnt;
-                            }
-                        }
-                    }
-                    const int pos = wave_alloc(cnt, &S.n[nb]);
-                    for (int j = 0; j < cnt; ++j) {
-                        const int32_t p = pos + j;
-                        if (p < A.list_cap) {
-                            L[nb].v[p] = v; L[nb].k[p] = ok[j]; L[nb].o[p] = oo[j];
-                            L[nb].w[p] = ow[j]; L[nb].t[p] = ot[j]; L[nb].d[p] = od[j];
-                        } else {
-                            atomicOr(&S.flags, F_LIST);
-                        }
-                    }
-                    adm += cnt;
-                }
-                if (adm) atomicAdd(&S.adm, (ull)adm);
-                {
-                    const int f = read_uniform(S.flags);
-                    if (f) { rflags = f; restart = true; break; }
-                }
-                const int32_t nn = S.n[nb];
-                // pages for admitted diagonals that have none yet
-                for (int32_t idx = tid; idx < nn; idx += BLOCK) {
-                    if (L[nb].d[idx] < 0) {
-                        bool ins;
-                        const int ds = dir_insert(dir, mask, dkey(L[nb].v[idx], L[nb].k[idx] >> 5), ins);
-                        if (ds < 0) atomicOr(&S.flags, F_GROW);
-                        else if (ins) { page_init(&pages[ds]); atomicAdd(&S.dirn, 1); }
-                        L[nb].d[idx] = ds;
-                    }
-                }
-                __syncthreads();
-                rflags = S.flags | ((S.dirn > (int32_t)((mask + 1) >> 1)) ? F_GROW : 0);
-                if (rflags) { restart = true; break; }
-                b = nb;
+                if (tid == 0) S.tick[3] += wall_clock64() - tk;
             }
         }
-        if (!restart) break;
+        if (status >= 0 || !(rflags)) break;
         // capacity exceeded: grow the directory if possible, else give up
-        const int fl = rflags;
         __syncthreads();
-        if ((fl & F_GROW) && !(fl & F_LIST) && cap_log2 + 2 <= A.dir_log2_max) {
-            cap_log2 += 2;
-            continue;
-        }
-        if ((fl & F_GROW) && !(fl & F_LIST) && cap_log2 < A.dir_log2_max) {
-            cap_log2 = A.dir_log2_max;
+        if ((rflags & F_GROW) && !(rflags & F_LIST) && cap_log2 < A.dir_log2_max) {
+            cap_log2 = min(cap_log2 + 2, A.dir_log2_max);
             continue;
         }
         status = GWFA_ST_ARENA;
         break;
     }
-    // ================= results and walk (Algorithm 6) =================
-    if (status == GWFA_ST_OK && tb) {
-        if (tid == 0) S.tend = -1;
-        __syncthreads();
-        const int32_t ev = (int32_t)(S.endkey >> 32), eo = (int32_t)(S.endkey & 0xffffffffull);
-        const int32_t n = S.n[b];
-        for (int32_t idx = tid; idx < n; idx += BLOCK)
-            if (L[b].v[idx] == ev && L[b].o[idx] == eo && L[b].k[idx] + eo == qlen) S.tend = L[b].t[idx];
-        __syncthreads();
-    }
+    if (chunks) atomicAdd(&S.chunks, (ull)chunks);
+    __syncthreads();
+    // ========== results and walk (Algorithm 6) ==========
     if (tid == 0) {
+        out->t_begin = t_begin;
+        out->t_end = (int64_t)wall_clock64();
         out->status = status;
         out->n_scores = s + 1;
         out->work = work;
@@ -587,14 +820,16 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             out->dist = s;
             out->end_v = (int32_t)(S.endkey >> 32);
             out->end_off = (int32_t)(S.endkey & 0xffffffffull);
-            if (tb && S.tend >= 0) {
+            if (q.tb && S.tend >= 0) {
+                // a chain visits each trace slot at most once: at most mask+1 steps
+                const int32_t lim = (int32_t)q.mask + 1;
                 int32_t len = 0;
-                for (int32_t t = S.tend; t >= 0; t = Tt[t]) ++len;
+                for (int32_t t = S.tend; t >= 0 && len <= lim; t = q.Tt[t]) ++len;
                 const ull pos = atomicAdd(A.path_cursor, (ull)len);
                 out->path_len = len;
                 if ((int64_t)pos + len <= A.path_cap && A.path_buf) {
                     int32_t j = len - 1;
-                    for (int32_t t = S.tend; t >= 0; t = Tt[t]) A.path_buf[pos + (j--)] = Tv[t];
+                    for (int32_t t = S.tend; t >= 0 && j >= 0; t = q.Tt[t]) A.path_buf[pos + (j--)] = q.Tv[t];
                     out->path_off = (int64_t)pos;
                 }
             }
@@ -613,13 +848,15 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             atomicAdd(&A.stats[4], S.adm);
             atomicAdd(&A.stats[6], S.mlp);
             atomicAdd(&A.stats[7], (ull)S.dropped);
+            atomicAdd(&A.stats[8], (ull)(s + 1));
+            for (int i = 0; i < 4; ++i) atomicAdd(&A.stats[9 + i], S.tick[i]);
         }
     }
     __syncthreads();
 }
 
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_align(KArgs A) {
+__global__ __launch_bounds__(BLOCK, 3) void k_align(KArgs A) {
     __shared__ Shared S;
     char* arena = A.arena + (int64_t)blockIdx.x * A.arena_stride;
     for (;;) {
@@ -690,6 +927,7 @@ hipError_t gwfa_launch_align(const KArgs& A, int lanes, int groups, hipStream_t 
     case 64: hipLaunchKernelGGL(gwfa_dev::k_align<64>, dim3(groups), dim3(64), 0, st, A); break;
     case 128: hipLaunchKernelGGL(gwfa_dev::k_align<128>, dim3(groups), dim3(128), 0, st, A); break;
     case 256: hipLaunchKernelGGL(gwfa_dev::k_align<256>, dim3(groups), dim3(256), 0, st, A); break;
+    case 512: hipLaunchKernelGGL(gwfa_dev::k_align<512>, dim3(groups), dim3(512), 0, st, A); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

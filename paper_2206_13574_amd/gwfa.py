@@ -29,8 +29,9 @@ ST_OK, ST_MAX_SCORE, ST_ARENA, ST_BAD_INPUT = 0, 1, 2, 3
 PRUNE_NONE, PRUNE_HEURISTIC, PRUNE_LEARNED = 0, 1, 2
 
 RESULT_DTYPE = np.dtype([("dist", "<i4"), ("end_v", "<i4"), ("end_off", "<i4"), ("status", "<i4"),
-                         ("path_off", "<i8"), ("path_len", "<i4"), ("n_scores", "<i4"), ("work", "<i8")])
-assert RESULT_DTYPE.itemsize == 40
+                         ("path_off", "<i8"), ("path_len", "<i4"), ("n_scores", "<i4"), ("work", "<i8"),
+                         ("t_begin", "<i8"), ("t_end", "<i8")])
+assert RESULT_DTYPE.itemsize == 56
 
 
 class Opts(ctypes.Structure):
@@ -138,9 +139,10 @@ class Context:
                self.h)
 
     def stats(self, reset: bool = False) -> dict:
-        out = np.zeros(8, dtype=np.int64)
+        out = np.zeros(16, dtype=np.int64)
         _check(_lib.gwfa_stats(self.h, _np_ptr(out), int(reset)), "gwfa_stats", self.h)
-        keys = ["entries", "crossings", "pages", "chunks", "admitted", "reruns", "mlp_evals", "pruned"]
+        keys = ["entries", "crossings", "pages", "chunks", "admitted", "reruns", "mlp_evals", "pruned", "scores",
+                "ticks_expand", "ticks_rounds", "ticks_merge", "ticks_prune", "r13", "r14", "r15"]
         return dict(zip(keys, out.tolist()))
 
     def mlp_load(self, bf16_weights: np.ndarray, feat_scale: np.ndarray):

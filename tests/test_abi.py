@@ -37,7 +37,7 @@ def test_host_only_calls():
     assert gwfa.packed_words(0) == 2 and gwfa.packed_words(1) == 3 and gwfa.packed_words(64) == 4
     o = gwfa.opts()
     assert (o.prune, o.traceback, o.max_score, o.end_vertex, o.mlp_period) == (0, 1, -1, -1, 1)
-    assert gwfa.RESULT_DTYPE.itemsize == 40
+    assert gwfa.RESULT_DTYPE.itemsize == 56
     for code in range(-8, 1):
         assert gwfa._lib.gwfa_strerror(code)
     # argument checks that return before touching a device
@@ -46,5 +46,5 @@ def test_host_only_calls():
     assert gwfa._lib.gwfa_ctx_create(0, None, None) == gwfa.ERR_ARG
     assert gwfa._lib.gwfa_align_batch(None, None, 0, None, None, None, None, None, None, 0, None) == gwfa.ERR_ARG
     assert gwfa._lib.gwfa_graph_create(None, 1, None, None, 0, None, None, None) == gwfa.ERR_ARG
-    stats = np.zeros(8, dtype=np.int64)
+    stats = np.zeros(16, dtype=np.int64)
     assert gwfa._lib.gwfa_stats(None, stats.ctypes.data_as(ctypes.c_void_p), 0) == gwfa.ERR_ARG
