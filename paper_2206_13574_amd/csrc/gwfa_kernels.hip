@@ -157,6 +157,15 @@ __device__ __forceinline__ int wave_alloc(int cnt, int* counter) {
     return base + ex;
 }
 
+// Workgroup barrier for phases that exchange only LDS data: waits for this
+// wave's LDS operations, not for its outstanding global stores (which the
+// full __syncthreads() would drain).
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // Exclusive prefix sum over the whole block in thread order (keeps lists
 // sorted).  All threads must call it.
 template <int BLOCK>
@@ -167,7 +176,7 @@ __device__ __forceinline__ int block_excl_scan(int x, int& total, int* scan) {
     const int w = threadIdx.x >> 6;
     if (NW == 1) { total = wt; return ex; }
     if (__lane_id() == 0) scan[w] = wt;
-    __syncthreads();
+    lds_barrier();
     int off = 0, tot = 0;
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
@@ -175,7 +184,7 @@ __device__ __forceinline__ int block_excl_scan(int x, int& total, int* scan) {
         off += (i < w) ? y : 0;
         tot += y;
     }
-    __syncthreads();
+    lds_barrier();
     total = tot;
     return off + ex;
 }
@@ -280,7 +289,8 @@ __device__ __forceinline__ int extend_entry(const KArgs& A, const Q& q, Shared& 
 }
 
 // Bitonic sort of n keys (+ payload) in place, ascending; n is a power of 2.
-template <int BLOCK>
+// LDS=true when keys and payload are in LDS (stages then need LDS barriers only).
+template <int BLOCK, bool LDS>
 __device__ void bitonic(ull* keys, int32_t* idx, int n) {
     for (int kk = 2; kk <= n; kk <<= 1) {
         for (int j = kk >> 1; j > 0; j >>= 1) {
@@ -295,7 +305,7 @@ __device__ void bitonic(ull* keys, int32_t* idx, int n) {
                     }
                 }
             }
-            __syncthreads();
+            if (LDS) lds_barrier(); else __syncthreads();
         }
     }
 }
@@ -309,6 +319,27 @@ __device__ __forceinline__ int32_t lower_bound_list(const Lists& L, int32_t n, u
     }
     return lo;
 }
+// Merged view of a list whose first n1 entries are sorted and whose last m
+// entries (crossing diagonals, unsorted in memory) have known merged
+// positions xpos[0..m) (ascending) at physical slots xidx[0..m).
+struct VMerge {
+    const int32_t* xpos;
+    const int32_t* xidx;
+    int32_t m;
+};
+// number of crossing entries whose merged position is below p
+__device__ __forceinline__ int32_t vm_below(const VMerge& vm, int32_t p) {
+    int32_t lo = 0, hi = vm.m;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (vm.xpos[mid] < p) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ int32_t vm_phys(const VMerge& vm, int32_t p, int32_t c) {
+    return (c < vm.m && vm.xpos[c] == p) ? vm.xidx[c] : p - c;
+}
+
 __device__ __forceinline__ int32_t lower_bound_keys(const ull* keys, int32_t n, ull key) {
     int32_t lo = 0, hi = n;
     while (lo < hi) {
@@ -318,9 +349,12 @@ __device__ __forceinline__ int32_t lower_bound_keys(const ull* keys, int32_t n, 
     return lo;
 }
 
-__device__ __forceinline__ void copy_entry(const Lists& a, int32_t i, const Lists& b, int32_t j) {
-    b.v[j] = a.v[i]; b.k[j] = a.k[i]; b.o[j] = a.o[i]; b.w[j] = a.w[i]; b.t[j] = a.t[i]; b.d[j] = a.d[i];
-    b.l[j] = a.l[i]; b.b[j] = a.b[i];
+// Copies entry i of a to slot j of b; W moves only when a pruning mode reads
+// it, t only when walks are traced.
+__device__ __forceinline__ void copy_entry(const Lists& a, int32_t i, const Lists& b, int32_t j, bool w, bool t) {
+    b.v[j] = a.v[i]; b.k[j] = a.k[i]; b.o[j] = a.o[i]; b.d[j] = a.d[i];
+    if (w) b.w[j] = a.w[i];
+    if (t) b.t[j] = a.t[i];
 }
 
 template <int BLOCK>
@@ -378,6 +412,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     int32_t s = 0;
     int cur = 1;
     int32_t n_cur = 0;
+    int32_t vmx = 0;          // crossing entries of the source list merged virtually
     int64_t work = 0;
     uint32_t chunks = 0;
     for (;;) {   // attempts with a growing directory
@@ -411,6 +446,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
         __syncthreads();
         cur = 1;
         n_cur = 0;
+        vmx = 0;
         s = 0;
         work = 0;
         status = -1;
@@ -427,6 +463,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 // ========== EXPAND (Algorithm 3) + EXTEND of what it admits ==========
                 const Lists Ls = LL(cur);
                 const int32_t n = n_cur;
+                VMerge vmv;
+                vmv.xpos = S.xcnt; vmv.xidx = S.sidx; vmv.m = vmx;
                 int32_t outbase = 0;
                 int adm = 0;
                 for (int32_t base = 0; base < n; base += BLOCK) {
@@ -439,37 +477,55 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     int32_t v = 0, k = 0, Lv = 0;
                     int64_t sb = 0;
                     if (idx < n) {
-                        v = Ls.v[idx];
-                        k = Ls.k[idx];
-                        const int32_t o0 = Ls.o[idx], W0 = Ls.w[idx], t0 = Ls.t[idx], ds0 = Ls.d[idx];
-                        sb = Ls.b[idx];
-                        Lv = Ls.l[idx];
+                        // physical slots of merged positions idx-2 .. idx+2
+                        int32_t pa2 = idx - 2, pa1 = idx - 1, p0 = idx, pb1 = idx + 1, pb2 = idx + 2;
+                        if (vmx) {
+                            const int32_t c0 = vm_below(vmv, idx);
+                            const int32_t c1 = c0 + ((c0 < vmv.m && vmv.xpos[c0] == idx) ? 1 : 0);
+                            const int32_t c2 = c1 + ((c1 < vmv.m && vmv.xpos[c1] == idx + 1) ? 1 : 0);
+                            const int32_t cm1 = c0 - ((c0 > 0 && vmv.xpos[c0 - 1] == idx - 1) ? 1 : 0);
+                            const int32_t cm2 = cm1 - ((cm1 > 0 && vmv.xpos[cm1 - 1] == idx - 2) ? 1 : 0);
+                            p0 = vm_phys(vmv, idx, c0);
+                            pb1 = vm_phys(vmv, idx + 1, c1);
+                            pb2 = vm_phys(vmv, idx + 2, c2);
+                            pa1 = vm_phys(vmv, idx - 1, cm1);
+                            pa2 = vm_phys(vmv, idx - 2, cm2);
+                        }
+                        v = Ls.v[p0];
+                        k = Ls.k[p0];
+                        const int32_t o0 = Ls.o[p0], ds0 = Ls.d[p0];
+                        const int32_t W0 = q.prune ? Ls.w[p0] : 0, t0 = q.tb ? Ls.t[p0] : -1;
+                        sb = seg_off[v];
+                        Lv = (int32_t)(seg_off[v + 1] - sb);
                         const int32_t i0 = k + o0;
                         // neighbours k-2, k-1, k+1, k+2 of the same vertex are
-                        // adjacent in the sorted list
+                        // adjacent in the (merged) sorted list
                         bool pm1 = false, pm2 = false, pp1 = false, pp2 = false;
                         int32_t o1 = 0, W1 = 0, t1 = 0, d1 = -1, o2 = 0, W2 = 0, t2 = 0;
-                        if (idx >= 1 && Ls.v[idx - 1] == v) {
-                            const int32_t ka = Ls.k[idx - 1];
+                        if (idx >= 1 && Ls.v[pa1] == v) {
+                            const int32_t ka = Ls.k[pa1];
                             if (ka == k - 1) {
                                 pm1 = true;
-                                pm2 = idx >= 2 && Ls.v[idx - 2] == v && Ls.k[idx - 2] == k - 2;
+                                pm2 = idx >= 2 && Ls.v[pa2] == v && Ls.k[pa2] == k - 2;
                             } else {
                                 pm2 = ka == k - 2;
                             }
                         }
-                        if (idx + 1 < n && Ls.v[idx + 1] == v) {
-                            const int32_t kc = Ls.k[idx + 1];
+                        if (idx + 1 < n && Ls.v[pb1] == v) {
+                            const int32_t kc = Ls.k[pb1];
                             if (kc == k + 1) {
                                 pp1 = true;
-                                o1 = Ls.o[idx + 1]; W1 = Ls.w[idx + 1]; t1 = Ls.t[idx + 1]; d1 = Ls.d[idx + 1];
-                                if (idx + 2 < n && Ls.v[idx + 2] == v && Ls.k[idx + 2] == k + 2) {
+                                o1 = Ls.o[pb1]; d1 = Ls.d[pb1];
+                                W1 = q.prune ? Ls.w[pb1] : 0; t1 = q.tb ? Ls.t[pb1] : -1;
+                                if (idx + 2 < n && Ls.v[pb2] == v && Ls.k[pb2] == k + 2) {
                                     pp2 = true;
-                                    o2 = Ls.o[idx + 2]; W2 = Ls.w[idx + 2]; t2 = Ls.t[idx + 2];
+                                    o2 = Ls.o[pb2];
+                                    W2 = q.prune ? Ls.w[pb2] : 0; t2 = q.tb ? Ls.t[pb2] : -1;
                                 }
                             } else if (kc == k + 2) {
                                 pp2 = true;
-                                o2 = Ls.o[idx + 1]; W2 = Ls.w[idx + 1]; t2 = Ls.t[idx + 1];
+                                o2 = Ls.o[pb1];
+                                W2 = q.prune ? Ls.w[pb1] : 0; t2 = q.tb ? Ls.t[pb1] : -1;
                             }
                         }
                         const int sl = k & 31;
@@ -571,8 +627,9 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                                 atomicOr(&S.flags, F_GROW);
                             } else {
                                 ncr = record_entry(A, q, S, v, kj, o, Wj, d, nw, Lv);
-                                Ld.v[p] = v; Ld.k[p] = kj; Ld.o[p] = o; Ld.w[p] = Wj; Ld.t[p] = tj; Ld.d[p] = d;
-                                Ld.l[p] = Lv; Ld.b[p] = sb;
+                                Ld.v[p] = v; Ld.k[p] = kj; Ld.o[p] = o; Ld.d[p] = d;
+                                if (q.prune) Ld.w[p] = Wj;
+                                if (q.tb) Ld.t[p] = tj;
                                 e0 = out_off[v];
                                 k2 = kj + Lv;
                             }
@@ -607,8 +664,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     if (idx < xhi) {
                         const int32_t v = Ld.v[idx], k = Ld.k[idx], d = Ld.d[idx];
                         int32_t o = Ld.o[idx];
-                        W = Ld.w[idx];
-                        t = Ld.t[idx];
+                        W = (q.prune || idx < preset_hi) ? Ld.w[idx] : 0;
+                        t = (q.tb || idx < preset_hi) ? Ld.t[idx] : -1;
                         if (idx >= preset_hi) {
                             if (q.prune) W = rval(q.pages[d].Wc[k & 31]);
                             t = q.tb ? trace_push(q, S, v, t) : -1;
@@ -616,7 +673,9 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         const int64_t sb = seg_off[v];
                         const int32_t Lv = (int32_t)(seg_off[v + 1] - sb);
                         ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, chunks);
-                        Ld.o[idx] = o; Ld.w[idx] = W; Ld.t[idx] = t; Ld.l[idx] = Lv; Ld.b[idx] = sb;
+                        Ld.o[idx] = o;
+                        if (q.prune) Ld.w[idx] = W;
+                        if (q.tb) Ld.t[idx] = t;
                         e0 = out_off[v];
                         k2 = k + Lv;
                     }
@@ -665,8 +724,9 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     const int pos = wave_alloc(claim, &S.n_out);
                     if (claim) {
                         if (pos < A.list_cap) {
-                            Ld.v[pos] = cu[c]; Ld.k[pos] = ck[c]; Ld.o[pos] = 0; Ld.w[pos] = cW[c]; Ld.t[pos] = ct[c];
-                            Ld.d[pos] = ds;
+                            Ld.v[pos] = cu[c]; Ld.k[pos] = ck[c]; Ld.o[pos] = 0; Ld.d[pos] = ds;
+                            if (q.prune) Ld.w[pos] = cW[c];
+                            if (q.tb) Ld.t[pos] = ct[c];
                         } else {
                             atomicOr(&S.flags, F_LIST);
                         }
@@ -707,60 +767,61 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             // inserted); a guard so that every workgroup finishes
             if (ntot == 0 || s > q.qlen + 1) { status = GWFA_ST_MAX_SCORE; break; }
             // ========== merge the crossing diagonals into the sorted list ==========
+            // Small sets (<= XS_LDS) are merged virtually: their keys are sorted
+            // in LDS and each gets its merged position (its rank among the
+            // crossing keys plus the number of expansion outputs below it);
+            // the next pass reads the list through that table.  Larger sets
+            // are sorted in the arena and the list is rewritten merged.
             const int32_t m = ntot - n1;
+            vmx = 0;
             if (m > 0) {
-                int N = 1;
-                while (N < m) N <<= 1;
-                ull* keys = (N <= XS_LDS) ? S.skeys : gkeys;
-                int32_t* sidx = (N <= XS_LDS) ? S.sidx : gidx;
-                if (N > A.sort_cap) { rflags = F_LIST; break; }
-                if (m <= 64) {
-                    // small set: each key's rank is the number of smaller keys
-                    for (int i = tid; i < m; i += BLOCK) S.skeys[i] = skey(Ld.v[n1 + i], Ld.k[n1 + i]);
-                    __syncthreads();
-                    for (int i = tid; i < m; i += BLOCK) {
-                        const ull ki = S.skeys[i];
-                        int32_t rk = 0;
-                        for (int j = 0; j < m; ++j) rk += S.skeys[j] < ki;
-                        S.skeys2[rk] = ki;
-                        S.sidx[rk] = n1 + i;
+                if (m > A.sort_cap) { rflags = F_LIST; break; }
+                if (m <= XS_LDS) {
+                    if (m <= 64) {
+                        for (int i = tid; i < m; i += BLOCK) S.skeys[i] = skey(Ld.v[n1 + i], Ld.k[n1 + i]);
+                        __syncthreads();
+                        for (int i = tid; i < m; i += BLOCK) {
+                            const ull ki = S.skeys[i];
+                            int32_t rk = 0;
+                            for (int j = 0; j < m; ++j) rk += S.skeys[j] < ki;
+                            S.skeys2[rk] = ki;
+                            S.sidx[rk] = n1 + i;
+                        }
+                        __syncthreads();
+                        for (int x = tid; x < m; x += BLOCK)
+                            S.xcnt[x] = x + lower_bound_list(Ld, n1, S.skeys2[x]);
+                    } else {
+                        int N = 1;
+                        while (N < m) N <<= 1;
+                        for (int i = tid; i < N; i += BLOCK) {
+                            S.skeys[i] = (i < m) ? skey(Ld.v[n1 + i], Ld.k[n1 + i]) : ~0ull;
+                            S.sidx[i] = n1 + i;
+                        }
+                        __syncthreads();
+                        bitonic<BLOCK, true>(S.skeys, S.sidx, N);
+                        for (int x = tid; x < m; x += BLOCK)
+                            S.xcnt[x] = x + lower_bound_list(Ld, n1, S.skeys[x]);
                     }
                     __syncthreads();
-                    keys = S.skeys2;
-                    sidx = S.sidx;
-                    N = m;
+                    vmx = m;
+                    cur = nb;
                 } else {
+                    int N = 1;
+                    while (N < m) N <<= 1;
+                    if (N > A.sort_cap) { rflags = F_LIST; break; }
                     for (int i = tid; i < N; i += BLOCK) {
-                        keys[i] = (i < m) ? skey(Ld.v[n1 + i], Ld.k[n1 + i]) : ~0ull;
-                        sidx[i] = n1 + i;
+                        gkeys[i] = (i < m) ? skey(Ld.v[n1 + i], Ld.k[n1 + i]) : ~0ull;
+                        gidx[i] = n1 + i;
                     }
                     __syncthreads();
-                    bitonic<BLOCK>(keys, sidx, N);
-                }
-                const Lists Lm = LL(cur);
-                if (N <= XS_LDS) {
-                    // main entry j lands at j + (crossing keys below it); crossing
-                    // entry x at x + (main keys below it), which is the first j
-                    // whose rank exceeds x (ranks do not decrease along the list)
-                    for (int32_t j = tid; j < n1; j += BLOCK) {
-                        const int32_t rj = lower_bound_keys(keys, m, skey(Ld.v[j], Ld.k[j]));
-                        const int32_t rp = (j == 0) ? 0 : lower_bound_keys(keys, m, skey(Ld.v[j - 1], Ld.k[j - 1]));
-                        for (int32_t x = rp; x < rj; ++x) S.xcnt[x] = j;
-                        if (j == n1 - 1)
-                            for (int32_t x = rj; x < m; ++x) S.xcnt[x] = n1;
-                        copy_entry(Ld, j, Lm, j + rj);
-                    }
-                    if (n1 == 0)
-                        for (int32_t x = tid; x < m; x += BLOCK) S.xcnt[x] = 0;
-                    __syncthreads();
-                    for (int32_t x = tid; x < m; x += BLOCK) copy_entry(Ld, sidx[x], Lm, x + S.xcnt[x]);
-                } else {
+                    bitonic<BLOCK, false>(gkeys, gidx, N);
+                    const Lists Lm = LL(cur);
                     for (int32_t j = tid; j < n1; j += BLOCK)
-                        copy_entry(Ld, j, Lm, j + lower_bound_keys(keys, m, skey(Ld.v[j], Ld.k[j])));
+                        copy_entry(Ld, j, Lm, j + lower_bound_keys(gkeys, m, skey(Ld.v[j], Ld.k[j])), q.prune, q.tb);
                     for (int32_t x = tid; x < m; x += BLOCK)
-                        copy_entry(Ld, sidx[x], Lm, x + lower_bound_list(Ld, n1, keys[x]));
+                        copy_entry(Ld, gidx[x], Lm, x + lower_bound_list(Ld, n1, gkeys[x]), q.prune, q.tb);
+                    __syncthreads();
                 }
-                __syncthreads();
             } else {
                 cur = nb;
             }
@@ -770,27 +831,32 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             if (A.prune == GWFA_PRUNE_HEURISTIC && amax > A.a_diff) {
                 const Lists Ls = LL(cur);
                 const Lists Lp = LL(1 - cur);
+                VMerge vmv;
+                vmv.xpos = S.xcnt; vmv.xidx = S.sidx; vmv.m = vmx;
                 int32_t outbase = 0;
                 int dropped = 0;
                 for (int32_t base = 0; base < n_cur; base += BLOCK) {
                     const int32_t idx = base + tid;
                     int keep = 0;
+                    int32_t ph = idx;
                     if (idx < n_cur) {
-                        const int32_t a = Ls.k[idx] + Ls.o[idx] + Ls.w[idx];
+                        if (vmx) ph = vm_phys(vmv, idx, vm_below(vmv, idx));
+                        const int32_t a = Ls.k[ph] + Ls.o[ph] + Ls.w[ph];
                         keep = (amax - a < A.a_diff) ? 1 : 0;
                         if (!keep) {   // the diagonal keeps its offset as its record
-                            q.pages[Ls.d[idx]].R[Ls.k[idx] & 31] = mkR(q.gen, Ls.o[idx]);
+                            q.pages[Ls.d[ph]].R[Ls.k[ph] & 31] = mkR(q.gen, Ls.o[ph]);
                             ++dropped;
                         }
                     }
                     int total;
                     const int pos = block_excl_scan<BLOCK>(keep, total, S.scan);
-                    if (keep) copy_entry(Ls, idx, Lp, outbase + pos);
+                    if (keep) copy_entry(Ls, ph, Lp, outbase + pos, q.prune, q.tb);
                     outbase += total;
                 }
                 if (dropped) atomicAdd(&S.dropped, dropped);
                 cur = 1 - cur;
                 n_cur = outbase;
+                vmx = 0;
                 __syncthreads();
                 if (tid == 0) S.tick[3] += wall_clock64() - tk;
             }
