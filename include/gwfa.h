@@ -55,8 +55,9 @@ extern "C" {
 /* ---- pruning modes (gwfa_opts.prune) ----------------------------------- */
 #define GWFA_PRUNE_NONE      0    /* exact: Algorithms 1-3                      */
 #define GWFA_PRUNE_HEURISTIC 1    /* Algorithm 4 before each expansion          */
-#define GWFA_PRUNE_LEARNED   2    /* MLP keep/drop per diagonal, fused in the
-                                     expansion (needs gwfa_mlp_load)            */
+#define GWFA_PRUNE_LEARNED   2    /* MLP keep/drop per diagonal before each
+                                     expansion (needs gwfa_mlp_load, else
+                                     GWFA_ERR_UNSUPPORTED)                      */
 
 typedef struct gwfa_ctx gwfa_ctx;       /* device, stream, working memory    */
 typedef struct gwfa_graph gwfa_graph;   /* packed labels + out-edge CSR      */
@@ -174,12 +175,83 @@ int gwfa_align_batch_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, co
                          const gwfa_opts *opts, gwfa_result *d_res, int32_t *d_path_buf, int64_t path_cap,
                          int64_t *d_path_used, void *hip_stream);
 
+/* The same, also writing one trace record per wavefront entry of every
+ * score that is expanded (all scores before the final one), taken after the
+ * extension and any pruning of that score, just before the expansion: the
+ * training data of the learned pruning network.  Record r of d_dump
+ * (device, 16 x 4 bytes, dump_cap records) holds
+ *   float f[8]   the entry's eight features before scaling (the inputs of
+ *                the network, see gwfa_mlp_load);
+ *   int32 read, score s, i, v, off, W (walk bases), k (= i - off), attempt.
+ * (i, v, off) is the entry's front cell: i query bases and off bases of v
+ * consumed (Eq. 2).  A query that restarts with more working memory writes
+ * its records again with a larger `attempt`; only the records of the largest
+ * attempt of a query belong to its final run.  *d_dump_count (device int64,
+ * cleared by the call) receives the number of records produced; those past
+ * dump_cap are not written.  Slower than gwfa_align_batch_dev; asynchronous
+ * under the same rule. */
+int gwfa_align_dump_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, const uint64_t *d_packed,
+                        const int64_t *d_read_off, const int32_t *d_v_start, const int32_t *d_order,
+                        const gwfa_opts *opts, gwfa_result *d_res, int32_t *d_path_buf, int64_t path_cap,
+                        int64_t *d_path_used, float *d_dump, int64_t dump_cap, int64_t *d_dump_count,
+                        void *hip_stream);
+
 /* Loads the pruning network used with GWFA_PRUNE_LEARNED: 8 features ->
  * 64 ReLU -> 64 ReLU -> 1 logit, bfloat16 values in the order W1[64][8],
  * b1[64], W2[64][64], b2[64], W3[64], b3 (4801 values), plus 8 float
- * feature scales (features are multiplied by them after log1p).
- * Host pointers, copied. */
+ * feature scales.  The network reads x = bf16(f * scale) for the features
+ *   f0 log1p(a_max - a)  (a = i + W, Algorithm 4)   f1 log1p(s)
+ *   f2 log1p(outdeg v)   f3 log1p(i_max - i)         f4 log1p(|v| - off)
+ *   f5 sign(W - i) log1p(|W - i|)   f6 i / |q|       f7 log1p(|q| - i)
+ * rounds each ReLU output to bfloat16 and sums in float32.  A diagonal is
+ * kept when its logit >= opts.keep_threshold; the diagonal with the largest
+ * a is always kept, and dropped diagonals keep their records (as in
+ * Algorithm 4).  Host pointers, copied. */
 int gwfa_mlp_load(gwfa_ctx *ctx, const uint16_t *bf16_weights, int64_t n, const float *feat_scale);
+
+/* ---- training of the pruning network (device buffers, asynchronous on
+ * `hip_stream`, NULL = context stream) ---------------------------------- */
+
+/* Mean gradient and mean loss of n samples: features d_feat (float, row r at
+ * d_feat + r * feat_stride, first 8 used, feat_stride >= 8), labels d_label
+ * (uint8, nonzero = keep), feat_scale (host, 8 floats), weights d_w (4801
+ * bfloat16).  Loss: binary cross-entropy on the logit, positives weighted by
+ * pos_weight > 0.  The forward pass is the alignment kernel's inference
+ * arithmetic; the backward pass treats the bfloat16 roundings as identities.
+ * Overwrites d_grad (4801 floats) and *d_loss (float). */
+int gwfa_mlp_grad_dev(gwfa_ctx *ctx, const float *d_feat, int64_t n, int64_t feat_stride, const uint8_t *d_label,
+                      const float *feat_scale, float pos_weight, const uint16_t *d_w, float *d_grad, float *d_loss,
+                      void *hip_stream);
+
+/* One Adam step (step >= 1 is the 1-based step count used for the bias
+ * corrections) on float32 master weights d_master with moments d_m1, d_m2
+ * (4801 floats each); writes the bfloat16 copy d_w. */
+int gwfa_mlp_adam_dev(gwfa_ctx *ctx, float *d_master, float *d_m1, float *d_m2, const float *d_grad,
+                      uint16_t *d_w, int32_t step, float lr, float beta1, float beta2, float eps, void *hip_stream);
+
+/* Rounds n floats to bfloat16 (nearest, ties to even). */
+int gwfa_mlp_cast_dev(gwfa_ctx *ctx, const float *d_src, uint16_t *d_dst, int64_t n, void *hip_stream);
+
+/* Logits of n samples computed by the alignment kernel's inference routine. */
+int gwfa_mlp_logits_dev(gwfa_ctx *ctx, const float *d_feat, int64_t n, int64_t feat_stride, const float *feat_scale,
+                        const uint16_t *d_w, float *d_out, void *hip_stream);
+
+/* Training labels (host computation, no device needed).  For trace records
+ * of exact runs (gwfa_align_dump_dev with GWFA_PRUNE_NONE) gives, per entry e
+ * with front cell (ent_i, ent_v, ent_off) of query ent_read at score
+ * ent_score, the cost out_cost[e] of the best completion of the alignment
+ * from that cell (Eq. 1 read from the end of the query; the end is free), and
+ * out_label[e] = [ent_score + out_cost = d*] (may be NULL): the entry lies on
+ * an optimal alignment.  out_dist[r] receives d* of query r.  The graph and
+ * queries are given as for gwfa_graph_create and gwfa_align_batch (host).
+ * Memory: two rows of (bases + n_vtx) int32 per thread.  n_threads <= 0: all
+ * hardware threads.  Returns GWFA_ERR_ARG for an entry outside its query or
+ * vertex. */
+int gwfa_label_entries(int32_t n_vtx, const uint8_t *seq, const int64_t *seq_off, int64_t n_edge,
+                       const int32_t *edge_src, const int32_t *edge_dst, int32_t n_reads, const uint8_t *reads,
+                       const int64_t *read_off, const int32_t *v_start, int64_t n_ent, const int32_t *ent_read,
+                       const int32_t *ent_score, const int32_t *ent_i, const int32_t *ent_v, const int32_t *ent_off,
+                       int32_t *out_cost, uint8_t *out_label, int32_t *out_dist, int32_t n_threads);
 
 /* Kernel-level counters accumulated since the last reset (device totals over
  * every query): [0] wavefront entries (sum |F_s|), [1] crossings admitted,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -14,13 +15,10 @@
 #include "gwfa.h"
 #include "gwfa_internal.h"
 
-#ifndef GWFA_HAVE_LEARNED
-#define GWFA_HAVE_LEARNED 0
-#endif
-
 namespace {
 
 constexpr int N_TIERS = 3;
+constexpr int64_t MLP_SCR_SAMPLES = 16384;
 
 struct Tier {
     int32_t dir_log2_max = 16;
@@ -75,6 +73,7 @@ struct gwfa_ctx {
     uint16_t* d_mlp = nullptr;
     float* d_mlp_scale = nullptr;
     bool mlp_loaded = false;
+    float* d_mlp_scr = nullptr;        // training activations, MLP_SCR_SAMPLES samples
     int n_cu = 256;
     std::string err;
 };
@@ -219,6 +218,7 @@ void gwfa_ctx_destroy(gwfa_ctx* c) {
     for (auto p : c->d_retry) if (p) (void)hipFree(p);
     if (c->d_mlp) (void)hipFree(c->d_mlp);
     if (c->d_mlp_scale) (void)hipFree(c->d_mlp_scale);
+    if (c->d_mlp_scr) (void)hipFree(c->d_mlp_scr);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -334,7 +334,7 @@ static int check_opts(const gwfa_ctx* ctx, const gwfa_opts* o) {
     if (o->prune < 0 || o->prune > 2) return GWFA_ERR_ARG;
     if (o->prune == GWFA_PRUNE_HEURISTIC && o->a_diff < 1) return GWFA_ERR_ARG;
     if (o->prune == GWFA_PRUNE_LEARNED) {
-        if (!ctx->mlp_loaded || !GWFA_HAVE_LEARNED) return GWFA_ERR_UNSUPPORTED;
+        if (!ctx->mlp_loaded) return GWFA_ERR_UNSUPPORTED;
         if (o->mlp_period < 1 || o->mlp_gate < 0) return GWFA_ERR_ARG;
     }
     if (o->max_score < -1) return GWFA_ERR_ARG;
@@ -342,10 +342,11 @@ static int check_opts(const gwfa_ctx* ctx, const gwfa_opts* o) {
     return GWFA_OK;
 }
 
-int gwfa_align_batch_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
-                         const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_order,
-                         const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
-                         int64_t* d_path_used, void* hip_stream) {
+static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
+                     const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_order,
+                     const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
+                     int64_t* d_path_used, float* d_dump, int64_t dump_cap, int64_t* d_dump_count,
+                     void* hip_stream) {
     if (!ctx || !g || n_reads < 0 || path_cap < 0) return GWFA_ERR_ARG;
     if (g->ctx && g->ctx->device != ctx->device) return GWFA_ERR_ARG;
     int rc = check_opts(ctx, opts);
@@ -374,14 +375,15 @@ int gwfa_align_batch_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, co
     A.keep_threshold = opts->keep_threshold; A.mlp_gate = opts->mlp_gate; A.mlp_period = opts->mlp_period;
     A.mlp_w = ctx->d_mlp; A.mlp_scale = ctx->d_mlp_scale;
     A.dir_factor = ctx->dir_factor;
+    A.dump = d_dump; A.dump_cap = d_dump ? dump_cap : 0; A.dump_count = (unsigned long long*)d_dump_count;
 
     const int32_t* order = d_order;
     int32_t n = n_reads;
-    HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, A.path_cursor, ctx->d_retry_count, st));
+    HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, A.path_cursor, ctx->d_retry_count, A.dump_count, st));
     for (int ti = 0; ti < N_TIERS; ++ti) {
         if ((rc = ensure_tier(ctx, ti))) return rc;
         const Tier& t = ctx->tier[ti];
-        A.order = order; A.n_reads = n;
+        A.order = order; A.n_reads = n; A.tier = ti;
         A.retry = (ti + 1 < N_TIERS) ? ctx->d_retry[ti & 1] : nullptr;
         A.arena = t.arena; A.arena_stride = t.stride;
         A.dir_log2_max = t.dir_log2_max; A.list_cap = t.list_cap; A.cand_cap = t.cand_cap; A.sort_cap = t.sort_cap;
@@ -398,9 +400,27 @@ int gwfa_align_batch_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, co
         order = ctx->d_retry[ti & 1];
         n = h_retry;
         // reset the queue and the retry counter, keep the path cursor
-        HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, nullptr, ctx->d_retry_count, st));
+        HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, nullptr, ctx->d_retry_count, nullptr, st));
     }
     return GWFA_OK;
+}
+
+int gwfa_align_batch_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
+                         const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_order,
+                         const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
+                         int64_t* d_path_used, void* hip_stream) {
+    return align_dev(ctx, g, n_reads, d_packed, d_read_off, d_v_start, d_order, opts, d_res, d_path_buf, path_cap,
+                     d_path_used, nullptr, 0, nullptr, hip_stream);
+}
+
+int gwfa_align_dump_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
+                        const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_order,
+                        const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
+                        int64_t* d_path_used, float* d_dump, int64_t dump_cap, int64_t* d_dump_count,
+                        void* hip_stream) {
+    if (!d_dump || dump_cap < 0 || !d_dump_count) return GWFA_ERR_ARG;
+    return align_dev(ctx, g, n_reads, d_packed, d_read_off, d_v_start, d_order, opts, d_res, d_path_buf, path_cap,
+                     d_path_used, d_dump, dump_cap, d_dump_count, hip_stream);
 }
 
 int gwfa_align_batch(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint8_t* reads,
@@ -489,11 +509,70 @@ int gwfa_align_batch(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
 int gwfa_mlp_load(gwfa_ctx* ctx, const uint16_t* w, int64_t n, const float* scale) {
     if (!ctx || !w || !scale || n != 4801) return GWFA_ERR_ARG;
     HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     if (!ctx->d_mlp) HIPCHK(ctx, hipMalloc((void**)&ctx->d_mlp, 4808 * 2));
     if (!ctx->d_mlp_scale) HIPCHK(ctx, hipMalloc((void**)&ctx->d_mlp_scale, 8 * 4));
     HIPCHK(ctx, hipMemcpy(ctx->d_mlp, w, (size_t)n * 2, hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemcpy(ctx->d_mlp_scale, scale, 8 * 4, hipMemcpyHostToDevice));
     ctx->mlp_loaded = true;
+    return GWFA_OK;
+}
+
+static bool get_scale(const float* h, Scale8& s) {
+    if (!h) return false;
+    for (int i = 0; i < 8; ++i) s.s[i] = h[i];
+    return true;
+}
+
+int gwfa_mlp_grad_dev(gwfa_ctx* ctx, const float* d_feat, int64_t n, int64_t feat_stride, const uint8_t* d_label,
+                      const float* feat_scale, float pos_weight, const uint16_t* d_w, float* d_grad, float* d_loss,
+                      void* hip_stream) {
+    Scale8 sc;
+    if (!ctx || n < 0 || feat_stride < 8 || !get_scale(feat_scale, sc) || !d_w || !d_grad || !d_loss ||
+        !(pos_weight > 0.0f))
+        return GWFA_ERR_ARG;
+    if (n > 0 && (!d_feat || !d_label)) return GWFA_ERR_ARG;
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if (!ctx->d_mlp_scr)
+        if (hipMalloc((void**)&ctx->d_mlp_scr, (size_t)gwfa_mlp_scratch_floats(MLP_SCR_SAMPLES) * 4) != hipSuccess) {
+            ctx->d_mlp_scr = nullptr;
+            return GWFA_ERR_NOMEM;
+        }
+    HIPCHK(ctx, gwfa_launch_mlp_grad(d_feat, feat_stride, sc, d_label, n, pos_weight, d_w, ctx->d_mlp_scr,
+                                     MLP_SCR_SAMPLES, d_grad, d_loss, st));
+    return GWFA_OK;
+}
+
+int gwfa_mlp_adam_dev(gwfa_ctx* ctx, float* d_master, float* d_m1, float* d_m2, const float* d_grad, uint16_t* d_w,
+                      int32_t step, float lr, float beta1, float beta2, float eps, void* hip_stream) {
+    if (!ctx || !d_master || !d_m1 || !d_m2 || !d_grad || !d_w || step < 1) return GWFA_ERR_ARG;
+    if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return GWFA_ERR_ARG;
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const float bc1 = 1.0f - (float)std::pow((double)beta1, (double)step);
+    const float bc2 = 1.0f - (float)std::pow((double)beta2, (double)step);
+    HIPCHK(ctx, gwfa_launch_mlp_adam(d_master, d_m1, d_m2, d_grad, d_w, lr, beta1, beta2, eps, bc1, bc2, st));
+    return GWFA_OK;
+}
+
+int gwfa_mlp_cast_dev(gwfa_ctx* ctx, const float* d_src, uint16_t* d_dst, int64_t n, void* hip_stream) {
+    if (!ctx || n < 0 || (n > 0 && (!d_src || !d_dst))) return GWFA_ERR_ARG;
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, gwfa_launch_mlp_cast(d_src, d_dst, n, st));
+    return GWFA_OK;
+}
+
+int gwfa_mlp_logits_dev(gwfa_ctx* ctx, const float* d_feat, int64_t n, int64_t feat_stride, const float* feat_scale,
+                        const uint16_t* d_w, float* d_out, void* hip_stream) {
+    Scale8 sc;
+    if (!ctx || n < 0 || feat_stride < 8 || !get_scale(feat_scale, sc) || !d_w) return GWFA_ERR_ARG;
+    if (n > 0 && (!d_feat || !d_out)) return GWFA_ERR_ARG;
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, gwfa_launch_mlp_logits(d_feat, feat_stride, sc, n, d_w, d_out, st));
     return GWFA_OK;
 }
 

@@ -33,6 +33,10 @@ struct KArgs {
     int32_t mlp_gate, mlp_period;
     const uint16_t* mlp_w;           // bf16 weights (device) or null
     const float* mlp_scale;          // 8 feature scales (device) or null
+    float* dump;                     // per-entry trace records (16 x 4 bytes) or null
+    int64_t dump_cap;
+    unsigned long long* dump_count;
+    int32_t tier;                    // working-memory tier of this launch (tags dump records)
     // working memory: one arena per workgroup
     char* arena;
     int64_t arena_stride;
@@ -43,4 +47,19 @@ struct KArgs {
 hipError_t gwfa_launch_align(const KArgs& A, int lanes, int groups, hipStream_t st);
 hipError_t gwfa_launch_pack(const uint8_t* ascii, int64_t n, unsigned long long* out, int64_t n_words,
                             int32_t* err, hipStream_t st);
-hipError_t gwfa_launch_reset(int32_t* queue, unsigned long long* cursor, int32_t* retry_count, hipStream_t st);
+hipError_t gwfa_launch_reset(int32_t* queue, unsigned long long* cursor, int32_t* retry_count,
+                             unsigned long long* dump_count, hipStream_t st);
+
+// pruning network: training and batch inference (gwfa_mlp.hip)
+struct Scale8 {
+    float s[8];
+};
+int64_t gwfa_mlp_scratch_floats(int64_t samples);
+hipError_t gwfa_launch_mlp_grad(const float* feat, int64_t stride, const Scale8& scale, const uint8_t* label,
+                                int64_t n, float pos_weight, const uint16_t* w, float* scr, int64_t scr_samples,
+                                float* grad, float* loss, hipStream_t st);
+hipError_t gwfa_launch_mlp_adam(float* master, float* m1, float* m2, const float* grad, uint16_t* wb, float lr,
+                                float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t st);
+hipError_t gwfa_launch_mlp_cast(const float* src, uint16_t* dst, int64_t n, hipStream_t st);
+hipError_t gwfa_launch_mlp_logits(const float* feat, int64_t stride, const Scale8& scale, int64_t n,
+                                  const uint16_t* w, float* out, hipStream_t st);

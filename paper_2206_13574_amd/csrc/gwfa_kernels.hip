@@ -35,8 +35,11 @@
 #include <stdint.h>
 
 #include "gwfa_internal.h"
+#include "gwfa_mlp_dev.h"
 
 namespace gwfa_dev {
+
+using namespace gwfa_nn;
 
 typedef unsigned long long ull;
 
@@ -230,6 +233,8 @@ struct Shared {
     int32_t sidx[XS_LDS];
     int32_t xcnt[XS_LDS];   // merge: main-list entries below each crossing entry
     ull skeys2[64];         // crossing keys sorted by rank counting (small sets)
+    uint16_t mlpw[4808];    // pruning network (bfloat16), loaded once per launch
+    float mscale[8];        // feature scales
 };
 
 // Per-query view of the arena and of the read.
@@ -244,7 +249,7 @@ struct Q {
     int32_t* Tt;
     uint32_t mask;
     uint32_t gen;
-    bool tb, prune;
+    bool tb, track;   // traced walks; walk lengths and lags tracked (pruning, dumps)
 };
 
 // Algorithm 5: T gets (v, t) unless the pair is already there; the index of
@@ -269,7 +274,7 @@ __device__ __forceinline__ int record_entry(const KArgs& A, const Q& q, Shared& 
         S.found = 1;
         if (o >= 1 || v == q.vs) atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
     }
-    if (q.prune) {
+    if (q.track) {
         atomicMax(&S.amax, i + W);
         atomicMax(&S.imax, i);
     }
@@ -357,7 +362,37 @@ __device__ __forceinline__ void copy_entry(const Lists& a, int32_t i, const List
     if (t) b.t[j] = a.t[i];
 }
 
-template <int BLOCK>
+// ---------------------------------------------------------------------------
+// Learned keep/drop of wavefront diagonals.
+//
+// Eight features of a diagonal whose front cell is (i, v, off) at score s,
+// with walk length W (a = i + W as in Algorithm 4), the largest a and i of the
+// wavefront, the label length |v| and out-degree of v:
+//   0 log1p(a_max - a)      lag behind the furthest diagonal
+//   1 log1p(s)              score
+//   2 log1p(outdeg(v))
+//   3 log1p(i_max - i)      distance from the query frontier
+//   4 log1p(|v| - off)      bases left in the vertex
+//   5 sign * log1p(|W - i|) walk/query drift (deletions minus insertions)
+//   6 i / |q|               progress
+//   7 log1p(|q| - i)        query left
+// each multiplied by a per-feature scale and rounded to bfloat16 before the
+// network (gwfa_mlp_dev.h) scores the diagonal.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void entry_features(float* f, int32_t s, int32_t i, int32_t W, int32_t off, int32_t Lv,
+                                               int32_t deg, int32_t amax, int32_t imax, int32_t qlen) {
+    f[0] = log1pf((float)(amax - (i + W)));
+    f[1] = log1pf((float)s);
+    f[2] = log1pf((float)deg);
+    f[3] = log1pf((float)(imax - i));
+    f[4] = log1pf((float)(Lv - off));
+    const int32_t dr = W - i;
+    f[5] = dr >= 0 ? log1pf((float)dr) : -log1pf((float)(-dr));
+    f[6] = qlen > 0 ? (float)i / (float)qlen : 0.0f;
+    f[7] = log1pf((float)(qlen - i));
+}
+
+template <int BLOCK, bool LEARN>
 __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shared& S) {
     const int tid = threadIdx.x;
     Q q;
@@ -384,7 +419,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     q.Tv = reinterpret_cast<int32_t*>(arena + A.o_tv);
     q.Tt = reinterpret_cast<int32_t*>(arena + A.o_tt);
     q.tb = A.traceback != 0;
-    q.prune = A.prune != GWFA_PRUNE_NONE;
+    q.track = A.prune != GWFA_PRUNE_NONE || A.dump != nullptr;
     uint32_t* hdr = reinterpret_cast<uint32_t*>(arena + A.o_hdr);
     int32_t* const lbase = reinterpret_cast<int32_t*>(arena + A.o_lists);
     const int64_t lcap = A.list_cap;
@@ -494,7 +529,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         v = Ls.v[p0];
                         k = Ls.k[p0];
                         const int32_t o0 = Ls.o[p0], ds0 = Ls.d[p0];
-                        const int32_t W0 = q.prune ? Ls.w[p0] : 0, t0 = q.tb ? Ls.t[p0] : -1;
+                        const int32_t W0 = q.track ? Ls.w[p0] : 0, t0 = q.tb ? Ls.t[p0] : -1;
                         sb = seg_off[v];
                         Lv = (int32_t)(seg_off[v + 1] - sb);
                         const int32_t i0 = k + o0;
@@ -516,16 +551,16 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             if (kc == k + 1) {
                                 pp1 = true;
                                 o1 = Ls.o[pb1]; d1 = Ls.d[pb1];
-                                W1 = q.prune ? Ls.w[pb1] : 0; t1 = q.tb ? Ls.t[pb1] : -1;
+                                W1 = q.track ? Ls.w[pb1] : 0; t1 = q.tb ? Ls.t[pb1] : -1;
                                 if (idx + 2 < n && Ls.v[pb2] == v && Ls.k[pb2] == k + 2) {
                                     pp2 = true;
                                     o2 = Ls.o[pb2];
-                                    W2 = q.prune ? Ls.w[pb2] : 0; t2 = q.tb ? Ls.t[pb2] : -1;
+                                    W2 = q.track ? Ls.w[pb2] : 0; t2 = q.tb ? Ls.t[pb2] : -1;
                                 }
                             } else if (kc == k + 2) {
                                 pp2 = true;
                                 o2 = Ls.o[pb1];
-                                W2 = q.prune ? Ls.w[pb1] : 0; t2 = q.tb ? Ls.t[pb1] : -1;
+                                W2 = q.track ? Ls.w[pb1] : 0; t2 = q.tb ? Ls.t[pb1] : -1;
                             }
                         }
                         const int sl = k & 31;
@@ -628,7 +663,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             } else {
                                 ncr = record_entry(A, q, S, v, kj, o, Wj, d, nw, Lv);
                                 Ld.v[p] = v; Ld.k[p] = kj; Ld.o[p] = o; Ld.d[p] = d;
-                                if (q.prune) Ld.w[p] = Wj;
+                                if (q.track) Ld.w[p] = Wj;
                                 if (q.tb) Ld.t[p] = tj;
                                 e0 = out_off[v];
                                 k2 = kj + Lv;
@@ -664,17 +699,17 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     if (idx < xhi) {
                         const int32_t v = Ld.v[idx], k = Ld.k[idx], d = Ld.d[idx];
                         int32_t o = Ld.o[idx];
-                        W = (q.prune || idx < preset_hi) ? Ld.w[idx] : 0;
+                        W = (q.track || idx < preset_hi) ? Ld.w[idx] : 0;
                         t = (q.tb || idx < preset_hi) ? Ld.t[idx] : -1;
                         if (idx >= preset_hi) {
-                            if (q.prune) W = rval(q.pages[d].Wc[k & 31]);
+                            if (q.track) W = rval(q.pages[d].Wc[k & 31]);
                             t = q.tb ? trace_push(q, S, v, t) : -1;
                         }
                         const int64_t sb = seg_off[v];
                         const int32_t Lv = (int32_t)(seg_off[v + 1] - sb);
                         ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, chunks);
                         Ld.o[idx] = o;
-                        if (q.prune) Ld.w[idx] = W;
+                        if (q.track) Ld.w[idx] = W;
                         if (q.tb) Ld.t[idx] = t;
                         e0 = out_off[v];
                         k2 = k + Lv;
@@ -718,14 +753,14 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             } else if (w == mine) {
                                 part = true;
                             }
-                            if (part && q.prune) atomicMax(&q.pages[ds].Wc[ck[c] & 31], mkR(q.gen, cW[c]));
+                            if (part && q.track) atomicMax(&q.pages[ds].Wc[ck[c] & 31], mkR(q.gen, cW[c]));
                         }
                     }
                     const int pos = wave_alloc(claim, &S.n_out);
                     if (claim) {
                         if (pos < A.list_cap) {
                             Ld.v[pos] = cu[c]; Ld.k[pos] = ck[c]; Ld.o[pos] = 0; Ld.d[pos] = ds;
-                            if (q.prune) Ld.w[pos] = cW[c];
+                            if (q.track) Ld.w[pos] = cW[c];
                             if (q.tb) Ld.t[pos] = ct[c];
                         } else {
                             atomicOr(&S.flags, F_LIST);
@@ -748,6 +783,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             __syncthreads();
             const int found = S.found;
             const int32_t amax = S.amax;
+            const int32_t imax = S.imax;
             __syncthreads();
             // ========== end test (extension mode) ==========
             if (found) {
@@ -817,9 +853,9 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     bitonic<BLOCK, false>(gkeys, gidx, N);
                     const Lists Lm = LL(cur);
                     for (int32_t j = tid; j < n1; j += BLOCK)
-                        copy_entry(Ld, j, Lm, j + lower_bound_keys(gkeys, m, skey(Ld.v[j], Ld.k[j])), q.prune, q.tb);
+                        copy_entry(Ld, j, Lm, j + lower_bound_keys(gkeys, m, skey(Ld.v[j], Ld.k[j])), q.track, q.tb);
                     for (int32_t x = tid; x < m; x += BLOCK)
-                        copy_entry(Ld, gidx[x], Lm, x + lower_bound_list(Ld, n1, gkeys[x]), q.prune, q.tb);
+                        copy_entry(Ld, gidx[x], Lm, x + lower_bound_list(Ld, n1, gkeys[x]), q.track, q.tb);
                     __syncthreads();
                 }
             } else {
@@ -850,7 +886,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     }
                     int total;
                     const int pos = block_excl_scan<BLOCK>(keep, total, S.scan);
-                    if (keep) copy_entry(Ls, ph, Lp, outbase + pos, q.prune, q.tb);
+                    if (keep) copy_entry(Ls, ph, Lp, outbase + pos, q.track, q.tb);
                     outbase += total;
                 }
                 if (dropped) atomicAdd(&S.dropped, dropped);
@@ -859,6 +895,73 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 vmx = 0;
                 __syncthreads();
                 if (tid == 0) S.tick[3] += wall_clock64() - tk;
+            }
+            // ========== trace dump and learned keep/drop ==========
+            const bool run_mlp = LEARN && A.prune == GWFA_PRUNE_LEARNED && n_cur >= A.mlp_gate && (s % A.mlp_period) == 0;
+            if (LEARN && (A.dump || run_mlp)) {
+                const Lists Ls = LL(cur);
+                const Lists Lp = LL(1 - cur);
+                VMerge vmv;
+                vmv.xpos = S.xcnt; vmv.xidx = S.sidx; vmv.m = vmx;
+                int32_t outbase = 0;
+                int dropped = 0, evals = 0;
+                for (int32_t base = 0; base < n_cur; base += BLOCK) {
+                    const int32_t idx = base + tid;
+                    int keep = 0;
+                    int32_t ph = idx;
+                    int rec = 0;
+                    float f[8];
+                    int32_t v = 0, k = 0, o = 0, W = 0, i = 0;
+                    if (idx < n_cur) {
+                        if (vmx) ph = vm_phys(vmv, idx, vm_below(vmv, idx));
+                        v = Ls.v[ph]; k = Ls.k[ph]; o = Ls.o[ph]; W = Ls.w[ph];
+                        i = k + o;
+                        const int32_t Lv = (int32_t)(seg_off[v + 1] - seg_off[v]);
+                        entry_features(f, s, i, W, o, Lv, out_off[v + 1] - out_off[v], amax, imax, q.qlen);
+                        rec = A.dump ? 1 : 0;
+                        keep = 1;
+                        if (run_mlp) {
+                            ++evals;
+                            const float z = mlp_logit(f, S.mscale, S.mlpw);
+                            keep = (z >= A.keep_threshold || i + W == amax) ? 1 : 0;   // the furthest diagonal stays
+                            if (!keep) {
+                                q.pages[Ls.d[ph]].R[k & 31] = mkR(q.gen, o);   // record kept, as in Algorithm 4
+                                ++dropped;
+                            }
+                        }
+                    }
+                    if (A.dump) {
+                        // one global atomic per wave
+                        int tot;
+                        const int ex = wave_excl_scan(rec, tot);
+                        ull b0 = 0;
+                        if (__lane_id() == 0 && tot > 0) b0 = atomicAdd(A.dump_count, (ull)tot);
+                        b0 = __shfl(b0, 0, 64);
+                        const ull slot = b0 + (ull)ex;
+                        if (rec && (int64_t)slot < A.dump_cap) {
+                            float* dr = A.dump + slot * 16;
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) dr[j] = f[j];
+                            int32_t* di = reinterpret_cast<int32_t*>(dr + 8);
+                            di[0] = r; di[1] = s; di[2] = i; di[3] = v; di[4] = o; di[5] = W; di[6] = k;
+                            di[7] = (A.tier << 8) | cap_log2;   // attempt: later attempts of a query supersede
+                        }
+                    }
+                    if (run_mlp) {
+                        int total;
+                        const int pos = block_excl_scan<BLOCK>(keep, total, S.scan);
+                        if (keep) copy_entry(Ls, ph, Lp, outbase + pos, q.track, q.tb);
+                        outbase += total;
+                    }
+                }
+                if (run_mlp) {
+                    if (dropped) atomicAdd(&S.dropped, dropped);
+                    if (evals) atomicAdd(&S.mlp, (ull)evals);
+                    cur = 1 - cur;
+                    n_cur = outbase;
+                    vmx = 0;
+                }
+                __syncthreads();
             }
         }
         if (status >= 0 || !(rflags)) break;
@@ -921,10 +1024,15 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     __syncthreads();
 }
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK, 3) void k_align(KArgs A) {
+template <int BLOCK, bool LEARN>
+__global__ __launch_bounds__(BLOCK, LEARN ? 2 : 3) void k_align(KArgs A) {
     __shared__ Shared S;
     char* arena = A.arena + (int64_t)blockIdx.x * A.arena_stride;
+    if (LEARN && A.prune == GWFA_PRUNE_LEARNED) {
+        for (int i = threadIdx.x; i < MLP_N; i += BLOCK) S.mlpw[i] = A.mlp_w[i];
+        if (threadIdx.x < 8) S.mscale[threadIdx.x] = A.mlp_scale[threadIdx.x];
+        __syncthreads();
+    }
     for (;;) {
         if (threadIdx.x == 0) S.read = atomicAdd(A.queue, 1);
         __syncthreads();
@@ -932,7 +1040,7 @@ __global__ __launch_bounds__(BLOCK, 3) void k_align(KArgs A) {
         __syncthreads();
         if (ridx >= A.n_reads) break;
         const int r = A.order ? A.order[ridx] : ridx;
-        align_read<BLOCK>(A, arena, r, S);
+        align_read<BLOCK, LEARN>(A, arena, r, S);
     }
 }
 
@@ -975,11 +1083,12 @@ __global__ void k_pack(const uint8_t* __restrict__ ascii, int64_t n, ull* __rest
     if (bad && err) atomicExch(err, (int32_t)GWFA_ERR_ALPHABET);
 }
 
-__global__ void k_reset(int32_t* queue, ull* path_cursor, int32_t* retry_count) {
+__global__ void k_reset(int32_t* queue, ull* path_cursor, int32_t* retry_count, ull* dump_count) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         *queue = 0;
         if (path_cursor) *path_cursor = 0;
         if (retry_count) *retry_count = 0;
+        if (dump_count) *dump_count = 0;
     }
 }
 
@@ -989,13 +1098,19 @@ __global__ void k_reset(int32_t* queue, ull* path_cursor, int32_t* retry_count) 
 // launch helpers (called from the host code)
 // ---------------------------------------------------------------------------
 hipError_t gwfa_launch_align(const KArgs& A, int lanes, int groups, hipStream_t st) {
+    // the learned keep/drop and the trace dump live in their own instantiation
+    const bool learn = A.prune == GWFA_PRUNE_LEARNED || A.dump != nullptr;
+#define GWFA_LAUNCH(L)                                                                                     \
+    if (learn) hipLaunchKernelGGL((gwfa_dev::k_align<L, true>), dim3(groups), dim3(L), 0, st, A);          \
+    else hipLaunchKernelGGL((gwfa_dev::k_align<L, false>), dim3(groups), dim3(L), 0, st, A);
     switch (lanes) {
-    case 64: hipLaunchKernelGGL(gwfa_dev::k_align<64>, dim3(groups), dim3(64), 0, st, A); break;
-    case 128: hipLaunchKernelGGL(gwfa_dev::k_align<128>, dim3(groups), dim3(128), 0, st, A); break;
-    case 256: hipLaunchKernelGGL(gwfa_dev::k_align<256>, dim3(groups), dim3(256), 0, st, A); break;
-    case 512: hipLaunchKernelGGL(gwfa_dev::k_align<512>, dim3(groups), dim3(512), 0, st, A); break;
+    case 64: GWFA_LAUNCH(64) break;
+    case 128: GWFA_LAUNCH(128) break;
+    case 256: GWFA_LAUNCH(256) break;
+    case 512: GWFA_LAUNCH(512) break;
     default: return hipErrorInvalidValue;
     }
+#undef GWFA_LAUNCH
     return hipGetLastError();
 }
 
@@ -1008,7 +1123,8 @@ hipError_t gwfa_launch_pack(const uint8_t* ascii, int64_t n, unsigned long long*
     return hipGetLastError();
 }
 
-hipError_t gwfa_launch_reset(int32_t* queue, unsigned long long* cursor, int32_t* retry_count, hipStream_t st) {
-    hipLaunchKernelGGL(gwfa_dev::k_reset, dim3(1), dim3(64), 0, st, queue, cursor, retry_count);
+hipError_t gwfa_launch_reset(int32_t* queue, unsigned long long* cursor, int32_t* retry_count,
+                             unsigned long long* dump_count, hipStream_t st) {
+    hipLaunchKernelGGL(gwfa_dev::k_reset, dim3(1), dim3(64), 0, st, queue, cursor, retry_count, dump_count);
     return hipGetLastError();
 }

@@ -57,9 +57,22 @@ _SIGS = {
     "gwfa_align_batch": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64, _P]),
     "gwfa_align_batch_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
                                             _P, _P]),
+    "gwfa_align_dump_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
+                                           _P, _P, _i64, _P, _P]),
     "gwfa_mlp_load": (ctypes.c_int, [_P, _P, _i64, _P]),
+    "gwfa_mlp_grad_dev": (ctypes.c_int, [_P, _P, _i64, _i64, _P, _P, ctypes.c_float, _P, _P, _P, _P]),
+    "gwfa_mlp_adam_dev": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _i32, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_float, _P]),
+    "gwfa_mlp_cast_dev": (ctypes.c_int, [_P, _P, _P, _i64, _P]),
+    "gwfa_mlp_logits_dev": (ctypes.c_int, [_P, _P, _i64, _i64, _P, _P, _P, _P]),
+    "gwfa_label_entries": (ctypes.c_int, [_i32, _P, _P, _i64, _P, _P, _i32, _P, _P, _P, _i64, _P, _P, _P, _P,
+                                          _P, _P, _P, _P, _i32]),
     "gwfa_stats": (ctypes.c_int, [_P, _P, _i32]),
 }
+
+MLP_N = 4801                      # parameters of the pruning network
+DUMP_WORDS = 16                   # 4-byte words per trace record
+DUMP_FIELDS = ("read", "score", "i", "v", "off", "W", "k", "attempt")
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
@@ -303,3 +316,122 @@ def align_host(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, pa
                                  _np_ptr(res), _np_ptr(path) if path_cap else None, int(path_cap),
                                  ctypes.byref(needed))
     return code, res[:n], path[:path_cap], int(needed.value)
+
+
+# ---- trace dumps and training of the pruning network -----------------------
+
+def align_dump_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts, dump, dump_count) -> None:
+    """align_dev that also writes one trace record per wavefront entry and
+    score into `dump` (float32 tensor [cap, 16]); `dump_count` (int64 [1])
+    receives the number of records produced."""
+    path_cap = int(out.path.numel()) if out.path is not None else 0
+    _check(_lib.gwfa_align_dump_dev(ctx.h, graph.h, batch.n, _tptr(batch.packed), _tptr(batch.read_off),
+                                    _tptr(batch.v_start), _tptr(batch.order), ctypes.byref(o), _tptr(out.res),
+                                    _tptr(out.path), path_cap, _tptr(out.path_used), _tptr(dump),
+                                    int(dump.shape[0]), _tptr(dump_count), _P(ctx.stream.cuda_stream)),
+           "gwfa_align_dump_dev", ctx.h)
+
+
+def split_dump(records: np.ndarray) -> dict:
+    """Host view of trace records (numpy float32 [n, 16]): features [n, 8]
+    and the integer fields."""
+    rec = np.ascontiguousarray(records, dtype=np.float32)
+    ints = rec[:, 8:16].view(np.int32)
+    d = {name: ints[:, j].copy() for j, name in enumerate(DUMP_FIELDS)}
+    d["feat"] = rec[:, :8].copy()
+    return d
+
+
+def final_attempt_mask(d: dict) -> np.ndarray:
+    """Records of the last attempt of each query (earlier attempts were
+    restarted with more working memory)."""
+    if len(d["read"]) == 0:
+        return np.zeros(0, dtype=bool)
+    last = np.full(int(d["read"].max()) + 1, -1, dtype=np.int64)
+    np.maximum.at(last, d["read"], d["attempt"].astype(np.int64))
+    return d["attempt"] == last[d["read"]]
+
+
+def mlp_grad_dev(ctx: Context, feat, label, scale: np.ndarray, w_bf16, grad, loss, pos_weight: float = 1.0,
+                 n: int = None) -> None:
+    """Mean loss gradient of the samples (feat float32 [n, stride>=8],
+    label uint8 [n]) for bfloat16 weights w_bf16 (int16/uint16 view, 4801);
+    overwrites grad (float32 [4801]) and loss (float32 [1])."""
+    n = int(feat.shape[0]) if n is None else int(n)
+    sc = np.ascontiguousarray(scale, dtype=np.float32)
+    _check(_lib.gwfa_mlp_grad_dev(ctx.h, _tptr(feat), n, int(feat.stride(0)), _tptr(label), _np_ptr(sc),
+                                  float(pos_weight), _tptr(w_bf16), _tptr(grad), _tptr(loss),
+                                  _P(ctx.stream.cuda_stream)), "gwfa_mlp_grad_dev", ctx.h)
+
+
+def mlp_adam_dev(ctx: Context, master, m1, m2, grad, w_bf16, step: int, lr: float, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8) -> None:
+    _check(_lib.gwfa_mlp_adam_dev(ctx.h, _tptr(master), _tptr(m1), _tptr(m2), _tptr(grad), _tptr(w_bf16),
+                                  int(step), float(lr), float(beta1), float(beta2), float(eps),
+                                  _P(ctx.stream.cuda_stream)), "gwfa_mlp_adam_dev", ctx.h)
+
+
+def mlp_cast_dev(ctx: Context, src, dst) -> None:
+    _check(_lib.gwfa_mlp_cast_dev(ctx.h, _tptr(src), _tptr(dst), int(src.numel()), _P(ctx.stream.cuda_stream)),
+           "gwfa_mlp_cast_dev", ctx.h)
+
+
+def mlp_logits_dev(ctx: Context, feat, scale: np.ndarray, w_bf16, out, n: int = None) -> None:
+    n = int(feat.shape[0]) if n is None else int(n)
+    sc = np.ascontiguousarray(scale, dtype=np.float32)
+    _check(_lib.gwfa_mlp_logits_dev(ctx.h, _tptr(feat), n, int(feat.stride(0)), _np_ptr(sc), _tptr(w_bf16),
+                                    _tptr(out), _P(ctx.stream.cuda_stream)), "gwfa_mlp_logits_dev", ctx.h)
+
+
+def label_entries(g, seq, off, v_start, read, score, i, v, offs, n_threads: int = 0):
+    """Host labels of trace entries (see gwfa_label_entries): returns
+    (cost, label, dist) numpy arrays."""
+    gseq = np.ascontiguousarray(np.frombuffer(g.seq, dtype=np.uint8) if isinstance(g.seq, (bytes, bytearray))
+                                else g.seq, dtype=np.uint8)
+    goff = np.ascontiguousarray(g.seg_off, dtype=np.int64)
+    src = np.ascontiguousarray(g.edge_src, dtype=np.int32)
+    dst = np.ascontiguousarray(g.edge_dst, dtype=np.int32)
+    seq = np.ascontiguousarray(np.frombuffer(seq, dtype=np.uint8) if isinstance(seq, (bytes, bytearray)) else seq,
+                               dtype=np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    vs = np.ascontiguousarray(v_start, dtype=np.int32)
+    cols = [np.ascontiguousarray(a, dtype=np.int32) for a in (read, score, i, v, offs)]
+    ne = len(cols[0])
+    cost = np.zeros(max(ne, 1), dtype=np.int32)
+    label = np.zeros(max(ne, 1), dtype=np.uint8)
+    dist = np.zeros(max(len(vs), 1), dtype=np.int32)
+    code = _lib.gwfa_label_entries(len(goff) - 1, _np_ptr(gseq), _np_ptr(goff), len(src), _np_ptr(src),
+                                   _np_ptr(dst), len(vs), _np_ptr(seq), _np_ptr(off), _np_ptr(vs), ne,
+                                   *[_np_ptr(c) for c in cols], _np_ptr(cost), _np_ptr(label), _np_ptr(dist),
+                                   int(n_threads))
+    _check(code, "gwfa_label_entries")
+    return cost[:ne], label[:ne], dist[:len(vs)]
+
+
+def align_dump(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, dump_cap: int = 1 << 22):
+    """Convenience: host queries in, (results, trace records as a dict of
+    numpy columns restricted to each query's final attempt, records
+    produced) out."""
+    if o is None:
+        o = opts(traceback=False)
+    torch = ctx.torch
+    seq = np.ascontiguousarray(np.frombuffer(seq, dtype=np.uint8) if isinstance(seq, (bytes, bytearray)) else seq,
+                               dtype=np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    n = len(off) - 1
+    batch = upload_reads(ctx, seq, off, v_start)
+    out = alloc_out(ctx, n, (int(off[-1]) + 64 * n) if o.traceback else 0)
+    dump = torch.empty((max(int(dump_cap), 1), DUMP_WORDS), dtype=torch.float32, device=ctx.tdev)
+    count = torch.zeros(1, dtype=torch.int64, device=ctx.tdev)
+    pack_dev(ctx, batch, out.err)
+    align_dump_dev(ctx, graph, batch, out, o, dump, count)
+    torch.cuda.synchronize(ctx.tdev)
+    if int(out.err.cpu().item()) != 0:
+        raise GwfaError(ERR_ALPHABET, "gwfa_pack_dev")
+    res, _, _ = fetch(out, n)
+    produced = int(count.cpu().item())
+    rec = dump[:min(produced, int(dump_cap))].cpu().numpy()
+    d = split_dump(rec)
+    keep = final_attempt_mask(d)
+    d = {k: v[keep] for k, v in d.items()}
+    return res, d, produced

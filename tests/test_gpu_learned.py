@@ -1,0 +1,211 @@
+"""GPU tests of the learned pruning mode: the trace dump, the training
+kernels (against the float64 reference of the network), the fused inference
+(keep-all weights reproduce the exact run; pruning never lowers a distance),
+and the options' guards."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp_ref as M
+from paper_2206_13574_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-learned] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def G(gpu_lib):
+    ctx = gpu_lib.Context(0)
+    yield gpu_lib, ctx
+    ctx.close()
+
+
+def _feats(rng, n):
+    """Feature rows shaped like the kernel's (log1p of counts, a fraction)."""
+    f = np.zeros((n, 8), np.float32)
+    f[:, 0] = np.log1p(rng.integers(0, 200, n))
+    f[:, 1] = np.log1p(rng.integers(0, 300, n))
+    f[:, 2] = np.log1p(rng.integers(0, 4, n))
+    f[:, 3] = np.log1p(rng.integers(0, 100, n))
+    f[:, 4] = np.log1p(rng.integers(0, 60, n))
+    d = rng.integers(-50, 50, n)
+    f[:, 5] = np.sign(d) * np.log1p(np.abs(d))
+    f[:, 6] = rng.random(n)
+    f[:, 7] = np.log1p(rng.integers(0, 1000, n))
+    return f
+
+
+def _bf16_tensor(torch, w64, dev):
+    return torch.from_numpy(M.bf16_bits(w64).view(np.int16).copy()).to(dev)
+
+
+def test_mlp_gradient_matches_float64_reference(G):
+    gw, ctx = G
+    torch = ctx.torch
+    rng = np.random.default_rng(9001)
+    for n, pw in ((1000, 1.0), (40000, 9.0)):   # one chunk; several chunks and a ragged tail
+        say(f"grad n={n} pos_weight={pw}")
+        w = M.init_params(rng)
+        w[M.O_B1:M.O_W2] = rng.normal(0, 0.2, 64)
+        w[M.O_B3] = -0.5
+        wq = M.bits_to_float(M.bf16_bits(w))
+        f = _feats(rng, n)
+        scale = (1.0 / np.array([5, 6, 2, 5, 4, 4, 1, 7], np.float32)).astype(np.float32)
+        y = (rng.random(n) < 0.2).astype(np.uint8)
+        dev = ctx.tdev
+        tf = torch.from_numpy(f).to(dev)
+        ty = torch.from_numpy(y).to(dev)
+        tw = _bf16_tensor(torch, w, dev)
+        grad = torch.full((M.N_PARAM,), 7.0, dtype=torch.float32, device=dev)   # overwritten
+        loss = torch.full((1,), 7.0, dtype=torch.float32, device=dev)
+        gw.mlp_grad_dev(ctx, tf, ty, scale, tw, grad, loss, pos_weight=pw)
+        torch.cuda.synchronize()
+        g_gpu = grad.cpu().numpy().astype(np.float64)
+        l_ref, g_ref = M.loss_and_grad(wq, M.inputs(f, scale), y, pw, round_act=True)
+        cos = g_gpu @ g_ref / (np.linalg.norm(g_gpu) * np.linalg.norm(g_ref))
+        rel = np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref)
+        say(f"  loss {float(loss.item()):.6f} vs {l_ref:.6f}; cos {cos:.7f}; rel {rel:.2e}")
+        assert abs(float(loss.item()) - l_ref) <= 1e-4 * max(1.0, abs(l_ref))
+        assert cos >= 0.999 and rel <= 2e-2
+
+
+def test_mlp_logits_match_reference_and_decisions_agree(G):
+    gw, ctx = G
+    torch = ctx.torch
+    rng = np.random.default_rng(9002)
+    n = 100000
+    w = M.init_params(rng)
+    w[M.O_B3] = 0.1
+    f = _feats(rng, n)
+    scale = np.full(8, 0.4, np.float32)
+    out = torch.zeros(n, dtype=torch.float32, device=ctx.tdev)
+    gw.mlp_logits_dev(ctx, torch.from_numpy(f).to(ctx.tdev), scale, _bf16_tensor(torch, w, ctx.tdev), out)
+    torch.cuda.synchronize()
+    z = out.cpu().numpy().astype(np.float64)
+    zr, _ = M.forward(M.bits_to_float(M.bf16_bits(w)), M.inputs(f, scale), round_act=True)
+    err = np.abs(z - zr)
+    say(f"logits max err {err.max():.3e}; mean |z| {np.abs(zr).mean():.3f}")
+    assert np.all(err <= 1e-3 * (1.0 + np.abs(zr)))
+    for tau in (-0.5, 0.0, 0.5):
+        agree = np.mean((z >= tau) == (zr >= tau))
+        assert agree >= 0.999, (tau, agree)
+
+
+def test_adam_and_cast_match_reference(G):
+    gw, ctx = G
+    torch = ctx.torch
+    rng = np.random.default_rng(9003)
+    dev = ctx.tdev
+    w = rng.normal(size=M.N_PARAM)
+    master = torch.from_numpy(w.astype(np.float32)).to(dev)
+    m1 = torch.zeros(M.N_PARAM, dtype=torch.float32, device=dev)
+    m2 = torch.zeros_like(m1)
+    wb = torch.zeros(M.N_PARAM, dtype=torch.int16, device=dev)
+    rw, rm1, rm2 = w.astype(np.float32).astype(np.float64), np.zeros(M.N_PARAM), np.zeros(M.N_PARAM)
+    for step in range(1, 6):
+        g = rng.normal(size=M.N_PARAM).astype(np.float32)
+        gw.mlp_adam_dev(ctx, master, m1, m2, torch.from_numpy(g).to(dev), wb, step, 1e-2)
+        rw, rm1, rm2 = M.adam_step(rw, rm1, rm2, g.astype(np.float64), step, 1e-2)
+    torch.cuda.synchronize()
+    got = master.cpu().numpy().astype(np.float64)
+    assert np.allclose(got, rw, rtol=1e-5, atol=1e-6)
+    assert np.array_equal(wb.cpu().numpy().view(np.uint16), M.bf16_bits(got))
+    wc = torch.zeros(M.N_PARAM, dtype=torch.int16, device=dev)
+    gw.mlp_cast_dev(ctx, master, wc)
+    torch.cuda.synchronize()
+    assert np.array_equal(wc.cpu().numpy(), wb.cpu().numpy())
+
+
+def _cfg1_subset():
+    g, r = synth.cfg1()
+    return g, r
+
+
+def test_dump_records_and_labels(G):
+    """Records per score equal the oracle's wavefront sizes; the features
+    recomputed from the integer fields match; every expanded score holds an
+    entry on an optimal alignment; the labels' d* equals the GPU's."""
+    gw, ctx = G
+    g, r = _cfg1_subset()
+    graph = gw.Graph.of(ctx, g)
+    seq = np.frombuffer(b"".join(r.read(i) for i in range(r.n)), dtype=np.uint8).copy()
+    off = np.asarray(r.off, dtype=np.int64)
+    say("dump cfg1")
+    res, d, produced = gw.align_dump(ctx, graph, seq, off, r.v_start, dump_cap=1 << 20)
+    graph.close()
+    assert produced == len(d["read"])        # cfg1 never restarts
+    lens = np.diff(np.asarray(g.seg_off))
+    outdeg = np.bincount(np.asarray(g.edge_src), minlength=g.n_vtx)
+    for k in range(r.n):
+        q = r.read(k)
+        sel = d["read"] == k
+        s, i, W, v, o, f = (d[x][sel] for x in ("score", "i", "W", "v", "off", "feat"))
+        dist = int(res[k]["dist"])
+        ref = O.gwf(g, q, int(r.v_start[k]), counts_cap=4096)
+        assert ref["dist"] == dist
+        assert np.array_equal(np.bincount(s, minlength=dist), ref["counts"][:dist]), k
+        assert np.array_equal(d["k"][sel], i - o)
+        for sc in range(dist):
+            m = s == sc
+            amax = (i[m] + W[m]).max()
+            imax = i[m].max()
+            want = np.stack([np.log1p(amax - i[m] - W[m]), np.log1p(np.full(m.sum(), sc)), np.log1p(outdeg[v[m]]),
+                             np.log1p(imax - i[m]), np.log1p(lens[v[m]] - o[m]),
+                             np.sign(W[m] - i[m]) * np.log1p(np.abs(W[m] - i[m])), i[m] / len(q),
+                             np.log1p(len(q) - i[m])], 1)
+            assert np.allclose(f[m], want, rtol=1e-5, atol=1e-6), (k, sc)
+    cost, label, dist = gw.label_entries(g, seq, off, r.v_start, d["read"], d["score"], d["i"], d["v"], d["off"])
+    assert np.array_equal(dist, res["dist"])
+    for k in range(r.n):
+        sel = d["read"] == k
+        assert set(d["score"][sel][label[sel] == 1].tolist()) == set(range(int(res[k]["dist"])))
+
+
+def _run(gw, ctx, g, r, o):
+    graph = gw.Graph.of(ctx, g)
+    seq = np.frombuffer(b"".join(r.read(i) for i in range(r.n)), dtype=np.uint8).copy()
+    res, paths = gw.align(ctx, graph, seq, np.asarray(r.off, dtype=np.int64), r.v_start, o)
+    graph.close()
+    return res, paths
+
+
+def test_learned_guards_keep_all_and_drop_all(G):
+    gw, ctx = G
+    g, r = synth.cfg2(n_reads=300)
+    say("exact cfg2[:300]")
+    ex, _ = _run(gw, ctx, g, r, gw.opts())
+    # no network loaded: learned mode is refused
+    ctx2 = gw.Context(0)
+    with pytest.raises(gw.GwfaError) as e:
+        _run(gw, ctx2, g, r, gw.opts(prune=gw.PRUNE_LEARNED))
+    assert e.value.code == gw.ERR_UNSUPPORTED
+    ctx2.close()
+    w = np.zeros(M.N_PARAM)
+    w[M.O_B3] = 10.0
+    ctx.mlp_load(M.bf16_bits(w), np.ones(8, np.float32))
+    ctx.stats(reset=True)
+    say("keep-all")
+    ka, paths = _run(gw, ctx, g, r, gw.opts(prune=gw.PRUNE_LEARNED, keep_threshold=0.0))
+    st = ctx.stats(reset=True)
+    assert np.array_equal(ka[["dist", "end_v", "end_off", "work", "status"]], ex[["dist", "end_v", "end_off", "work", "status"]])
+    assert st["mlp_evals"] > 0 and st["pruned"] == 0
+    w[M.O_B3] = -10.0
+    ctx.mlp_load(M.bf16_bits(w), np.ones(8, np.float32))
+    for gate, period in ((0, 1), (64, 4)):
+        say(f"drop-all gate={gate} period={period}")
+        da, paths = _run(gw, ctx, g, r, gw.opts(prune=gw.PRUNE_LEARNED, mlp_gate=gate, mlp_period=period))
+        st = ctx.stats(reset=True)
+        assert (da["status"] == 0).all() and (da["dist"] >= ex["dist"]).all()
+        assert st["pruned"] > 0 and da["work"].sum() < ex["work"].sum()
+        seqs = [r.read(i) for i in range(r.n)]
+        for k in range(0, r.n, 37):   # walks stay valid alignments of the reported cost
+            p = paths[k]
+            assert O.is_walk(g, p) and p[0] == r.v_start[k] and p[-1] == da[k]["end_v"]
+            assert O.ed_global(seqs[k], O.spell_walk(g, p, int(da[k]["end_off"]))) == da[k]["dist"]
+    # a gate above every wavefront size never runs the network: exact
+    ng, _ = _run(gw, ctx, g, r, gw.opts(prune=gw.PRUNE_LEARNED, mlp_gate=1 << 30))
+    st = ctx.stats(reset=True)
+    assert st["mlp_evals"] == 0 and np.array_equal(ng["dist"], ex["dist"]) and np.array_equal(ng["work"], ex["work"])

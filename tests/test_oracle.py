@@ -310,3 +310,26 @@ def test_reverse_labels_consistency(cfg1):
                                 O._ptr(cost), 1, O._ptr(dst))
         assert rc == 0
         assert int(dst[0]) == O.dp_dense(g, q, vs)[0] == int(cost[0])
+
+
+def test_reverse_labels_equal_forward_suffix_runs():
+    """R(i, v, 0) is d* of the query suffix q[i+1..] started at (v, 0): the
+    reverse recurrence pinned cell by cell against the forward oracle (itself
+    pinned by brute force), on random cyclic graphs."""
+    rng = np.random.default_rng(8101)
+    lib = O._load()
+    for case in range(60):
+        g = synth.small_random_graph(rng, int(rng.integers(1, 6)), max_label=4, p_edge=0.35, cyclic=True)
+        G = O.OGraph.of(g)
+        q = "".join("ACGT"[x] for x in rng.integers(0, 4, size=int(rng.integers(0, 9)))).encode()
+        vs = int(rng.integers(0, g.n_vtx))
+        ei = np.array([i for i in range(len(q) + 1) for v in range(g.n_vtx)], dtype=np.int32)
+        ev = np.array([v for i in range(len(q) + 1) for v in range(g.n_vtx)], dtype=np.int32)
+        eo = np.zeros(len(ei), dtype=np.int32)
+        cost = np.zeros(len(ei), dtype=np.int32)
+        dst = np.zeros(1, dtype=np.int32)
+        qa = np.frombuffer(q, dtype=np.uint8).copy()
+        assert lib.orc_rev_labels(*G._args(), O._ptr(qa), len(qa), vs, O._ptr(ei), O._ptr(ev), O._ptr(eo),
+                                  O._ptr(cost), len(ei), O._ptr(dst)) == 0
+        for e in range(len(ei)):
+            assert int(cost[e]) == O.dp_dense(g, q[int(ei[e]):], int(ev[e]))[0], (case, e)
