@@ -79,7 +79,7 @@ struct gwfa_ctx {
 };
 
 struct gwfa_graph {
-    gwfa_ctx* ctx = nullptr;
+    int device = 0;                    // the graph does not depend on the context that built it
     int32_t n_vtx = 0;
     int64_t n_edge = 0;
     int64_t bases = 0;
@@ -273,7 +273,7 @@ int gwfa_graph_create(gwfa_ctx* ctx, int32_t n_vtx, const uint8_t* seq, const in
     }
     gwfa_graph* g = new (std::nothrow) gwfa_graph();
     if (!g) return GWFA_ERR_NOMEM;
-    g->ctx = ctx; g->n_vtx = n_vtx; g->n_edge = n_edge; g->bases = bases;
+    g->device = ctx->device; g->n_vtx = n_vtx; g->n_edge = n_edge; g->bases = bases;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     const int64_t words = gwfa_packed_words(bases);
     uint8_t* d_ascii = nullptr;
@@ -311,7 +311,7 @@ int gwfa_graph_create(gwfa_ctx* ctx, int32_t n_vtx, const uint8_t* seq, const in
 
 void gwfa_graph_destroy(gwfa_graph* g) {
     if (!g) return;
-    if (g->ctx) (void)hipSetDevice(g->ctx->device);
+    (void)hipSetDevice(g->device);
     if (g->d_seg) (void)hipFree(g->d_seg);
     if (g->d_seg_off) (void)hipFree(g->d_seg_off);
     if (g->d_out_off) (void)hipFree(g->d_out_off);
@@ -348,7 +348,7 @@ static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
                      int64_t* d_path_used, float* d_dump, int64_t dump_cap, int64_t* d_dump_count,
                      void* hip_stream) {
     if (!ctx || !g || n_reads < 0 || path_cap < 0) return GWFA_ERR_ARG;
-    if (g->ctx && g->ctx->device != ctx->device) return GWFA_ERR_ARG;
+    if (g->device != ctx->device) return GWFA_ERR_ARG;
     int rc = check_opts(ctx, opts);
     if (rc) return rc;
     if (n_reads == 0) return GWFA_OK;

@@ -1100,6 +1100,7 @@ __global__ void k_reset(int32_t* queue, ull* path_cursor, int32_t* retry_count, 
 hipError_t gwfa_launch_align(const KArgs& A, int lanes, int groups, hipStream_t st) {
     // the learned keep/drop and the trace dump live in their own instantiation
     const bool learn = A.prune == GWFA_PRUNE_LEARNED || A.dump != nullptr;
+    (void)hipGetLastError();   // the launch status below must not report an older, unrelated error
 #define GWFA_LAUNCH(L)                                                                                     \
     if (learn) hipLaunchKernelGGL((gwfa_dev::k_align<L, true>), dim3(groups), dim3(L), 0, st, A);          \
     else hipLaunchKernelGGL((gwfa_dev::k_align<L, false>), dim3(groups), dim3(L), 0, st, A);
@@ -1119,12 +1120,14 @@ hipError_t gwfa_launch_pack(const uint8_t* ascii, int64_t n, unsigned long long*
     if (n_words <= 0) return hipSuccess;
     const int tpb = 256;
     const int64_t blocks = (n_words + tpb - 1) / tpb;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(gwfa_dev::k_pack, dim3((unsigned)blocks), dim3(tpb), 0, st, ascii, n, out, n_words, err);
     return hipGetLastError();
 }
 
 hipError_t gwfa_launch_reset(int32_t* queue, unsigned long long* cursor, int32_t* retry_count,
                              unsigned long long* dump_count, hipStream_t st) {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(gwfa_dev::k_reset, dim3(1), dim3(64), 0, st, queue, cursor, retry_count, dump_count);
     return hipGetLastError();
 }

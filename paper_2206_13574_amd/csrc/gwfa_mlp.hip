@@ -171,6 +171,7 @@ hipError_t gwfa_launch_mlp_grad(const float* feat, int64_t stride, const Scale8&
                                 int64_t n, float pos_weight, const uint16_t* w, float* scr, int64_t scr_samples,
                                 float* grad, float* loss, hipStream_t st) {
     using namespace gwfa_train;
+    (void)hipGetLastError();   // report only this call's launch status
     hipLaunchKernelGGL(k_zero, dim3((MLP_N + 255) / 256), dim3(256), 0, st, grad, MLP_N);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, loss, 1);
     if (n <= 0) return hipGetLastError();
@@ -188,6 +189,7 @@ hipError_t gwfa_launch_mlp_grad(const float* feat, int64_t stride, const Scale8&
 hipError_t gwfa_launch_mlp_adam(float* master, float* m1, float* m2, const float* grad, uint16_t* wb, float lr,
                                 float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t st) {
     using namespace gwfa_train;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_adam, dim3((MLP_N + 255) / 256), dim3(256), 0, st, master, m1, m2, grad, wb, lr, beta1,
                        beta2, eps, bc1, bc2);
     return hipGetLastError();
@@ -195,6 +197,7 @@ hipError_t gwfa_launch_mlp_adam(float* master, float* m1, float* m2, const float
 
 hipError_t gwfa_launch_mlp_cast(const float* src, uint16_t* dst, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(gwfa_train::k_cast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
     return hipGetLastError();
 }
@@ -202,6 +205,7 @@ hipError_t gwfa_launch_mlp_cast(const float* src, uint16_t* dst, int64_t n, hipS
 hipError_t gwfa_launch_mlp_logits(const float* feat, int64_t stride, const Scale8& scale, int64_t n,
                                   const uint16_t* w, float* out, hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(gwfa_train::k_logits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, feat, stride, scale,
                        n, w, out);
     return hipGetLastError();

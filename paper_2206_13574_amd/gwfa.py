@@ -19,6 +19,10 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2206_13574_amd/build.py "
                       "(or __graft_entry__.build()); there is no fallback path")
 
+# torch first: the library then binds to the HIP runtime torch has loaded,
+# so both use one runtime (one set of devices, streams and allocations)
+import torch as _torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- error / status codes (include/gwfa.h) ---------------------------------

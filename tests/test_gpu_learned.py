@@ -166,10 +166,11 @@ def test_dump_records_and_labels(G):
 
 def _run(gw, ctx, g, r, o):
     graph = gw.Graph.of(ctx, g)
-    seq = np.frombuffer(b"".join(r.read(i) for i in range(r.n)), dtype=np.uint8).copy()
-    res, paths = gw.align(ctx, graph, seq, np.asarray(r.off, dtype=np.int64), r.v_start, o)
-    graph.close()
-    return res, paths
+    try:
+        seq = np.frombuffer(b"".join(r.read(i) for i in range(r.n)), dtype=np.uint8).copy()
+        return gw.align(ctx, graph, seq, np.asarray(r.off, dtype=np.int64), r.v_start, o)
+    finally:
+        graph.close()
 
 
 def test_learned_guards_keep_all_and_drop_all(G):
@@ -201,11 +202,27 @@ def test_learned_guards_keep_all_and_drop_all(G):
         assert (da["status"] == 0).all() and (da["dist"] >= ex["dist"]).all()
         assert st["pruned"] > 0 and da["work"].sum() < ex["work"].sum()
         seqs = [r.read(i) for i in range(r.n)]
-        for k in range(0, r.n, 37):   # walks stay valid alignments of the reported cost
+        for k in range(0, r.n, 37):
+            # a pruned search may align the query to its walk suboptimally: the walk is a witness
+            # whose best alignment costs between d* and the reported distance
             p = paths[k]
             assert O.is_walk(g, p) and p[0] == r.v_start[k] and p[-1] == da[k]["end_v"]
-            assert O.ed_global(seqs[k], O.spell_walk(g, p, int(da[k]["end_off"]))) == da[k]["dist"]
+            e = O.ed_global(seqs[k], O.spell_walk(g, p, int(da[k]["end_off"])))
+            assert ex[k]["dist"] <= e <= da[k]["dist"]
     # a gate above every wavefront size never runs the network: exact
     ng, _ = _run(gw, ctx, g, r, gw.opts(prune=gw.PRUNE_LEARNED, mlp_gate=1 << 30))
     st = ctx.stats(reset=True)
     assert st["mlp_evals"] == 0 and np.array_equal(ng["dist"], ex["dist"]) and np.array_equal(ng["work"], ex["work"])
+
+
+def test_graph_outlives_its_context(G):
+    """A graph destroyed after the context that built it: no stale state is
+    left behind for the next calls (regression)."""
+    gw, ctx = G
+    g, r = synth.cfg1()
+    ctx2 = gw.Context(0)
+    graph2 = gw.Graph.of(ctx2, g)
+    ctx2.close()
+    graph2.close()
+    res, _ = _run(gw, ctx, g, r.subset(range(5)), gw.opts())
+    assert (res["status"] == 0).all()
