@@ -92,6 +92,12 @@ def init_params(rng) -> np.ndarray:
     return w
 
 
+def to_bf16_bits(w: np.ndarray) -> np.ndarray:
+    """float -> bfloat16 bit patterns (nearest, ties to even)."""
+    u = np.ascontiguousarray(w, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
 def feature_scale(f: np.ndarray) -> np.ndarray:
     q = np.quantile(np.abs(f), 0.999, axis=0)
     return (1.0 / np.maximum(q, 1e-3)).astype(np.float32)

@@ -226,3 +226,48 @@ def test_graph_outlives_its_context(G):
     graph2.close()
     res, _ = _run(gw, ctx, g, r.subset(range(5)), gw.opts())
     assert (res["status"] == 0).all()
+
+
+def test_trained_network_gain_on_cyclic_workload(G):
+    """The committed network (trained on acyclic 1 kb traces, threshold
+    calibrated on held-out acyclic graphs) on the cyclic 100 kb workload:
+    faster than exact with at most 1% of reads above the exact distance; an
+    untrained network of the same shape at the same threshold does not
+    achieve that."""
+    gw, ctx = G
+    from paper_2206_13574_amd import train_prune
+    torch = ctx.torch
+    W = train_prune.load()
+    g, r = synth.cfg3()
+    r = r.subset(np.arange(400))
+    graph = gw.Graph.of(ctx, g)
+    batch = gw.upload_reads(ctx, r.seq, r.off, r.v_start)
+    out = gw.alloc_out(ctx, r.n, 0)
+    gw.pack_dev(ctx, batch, out.err)
+
+    def timed(o):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        gw.align_dev(ctx, graph, batch, out, o)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), gw.fetch(out, r.n)[0]
+
+    say("cfg3[:400] exact")
+    t_ex, ex = timed(gw.opts(traceback=False))
+    lo = gw.opts(prune=gw.PRUNE_LEARNED, keep_threshold=W["tau"], mlp_gate=W["gate"], mlp_period=W["period"],
+                 traceback=False)
+    ctx.mlp_load(W["w_bf16"], W["scale"])
+    say("trained network")
+    t_le, le = timed(lo)
+    ctx.mlp_load(train_prune.to_bf16_bits(train_prune.init_params(np.random.default_rng(4242))), W["scale"])
+    say("untrained network")
+    t_un, un = timed(lo)
+    graph.close()
+    assert (ex["status"] == 0).all() and (le["status"] == 0).all() and (un["status"] == 0).all()
+    over = lambda res: float(np.mean(res["dist"] > ex["dist"]))
+    say(f"exact {t_ex:.1f} ms; trained {t_le:.1f} ms, over {over(le):.4f}; untrained {t_un:.1f} ms, "
+        f"over {over(un):.4f}")
+    assert (le["dist"] >= ex["dist"]).all() and (un["dist"] >= ex["dist"]).all()
+    assert t_le < t_ex / 2 and over(le) <= 0.01
+    assert not (t_un < t_ex / 2 and over(un) <= 0.01)
