@@ -196,6 +196,28 @@ int gwfa_align_dump_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, con
                         int64_t *d_path_used, float *d_dump, int64_t dump_cap, int64_t *d_dump_count,
                         void *hip_stream);
 
+/* ---- captured launches ---------------------------------------------------
+ * A plan records the alignment of one device-resident batch (the arguments
+ * of gwfa_align_batch_dev, fixed at creation) as a HIP graph: the reset of
+ * the work queue and counters and the first-tier launch of the persistent
+ * alignment kernel, kernels only.  gwfa_plan_launch replays it on
+ * `hip_stream` (NULL = context stream), asynchronously, with no host work.
+ * gwfa_plan_finish then synchronises that stream and re-runs, eagerly, the
+ * queries that overflowed the first tier's working memory (usually none);
+ * after it returns, results are complete exactly as after
+ * gwfa_align_batch_dev.  The buffers named at creation must stay allocated;
+ * gwfa_ctx_config invalidates the plan (its calls then return GWFA_ERR_ARG);
+ * destroy plans before their context.  Replays of one plan, like calls on one
+ * context, must not overlap in time. */
+typedef struct gwfa_plan gwfa_plan;
+int gwfa_plan_create(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, const uint64_t *d_packed,
+                     const int64_t *d_read_off, const int32_t *d_v_start, const int32_t *d_order,
+                     const gwfa_opts *opts, gwfa_result *d_res, int32_t *d_path_buf, int64_t path_cap,
+                     int64_t *d_path_used, gwfa_plan **out);
+int gwfa_plan_launch(gwfa_plan *plan, void *hip_stream);
+int gwfa_plan_finish(gwfa_plan *plan, void *hip_stream);
+void gwfa_plan_destroy(gwfa_plan *plan);
+
 /* Loads the pruning network used with GWFA_PRUNE_LEARNED: 8 features ->
  * 64 ReLU -> 64 ReLU -> 1 logit, bfloat16 values in the order W1[64][8],
  * b1[64], W2[64][64], b2[64], W3[64], b3 (4801 values), plus 8 float

@@ -74,6 +74,7 @@ struct gwfa_ctx {
     float* d_mlp_scale = nullptr;
     bool mlp_loaded = false;
     float* d_mlp_scr = nullptr;        // training activations, MLP_SCR_SAMPLES samples
+    int64_t epoch = 0;                 // bumped when working memory is freed (invalidates plans)
     int n_cu = 256;
     std::string err;
 };
@@ -237,6 +238,7 @@ int gwfa_ctx_config(gwfa_ctx* c, int32_t lanes, int32_t n_groups, int32_t dir_lo
     c->groups = n_groups;
     c->dir_factor = dir_factor;
     set_tiers(c, dir_log2_max, list_cap);
+    c->epoch++;
     return GWFA_OK;
 }
 
@@ -342,20 +344,16 @@ static int check_opts(const gwfa_ctx* ctx, const gwfa_opts* o) {
     return GWFA_OK;
 }
 
-static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
-                     const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_order,
-                     const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
-                     int64_t* d_path_used, float* d_dump, int64_t dump_cap, int64_t* d_dump_count,
-                     void* hip_stream) {
+// Launch arguments common to every tier of one batch.
+static int fill_args(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
+                     const int64_t* d_read_off, const int32_t* d_v_start, const gwfa_opts* opts, gwfa_result* d_res,
+                     int32_t* d_path_buf, int64_t path_cap, int64_t* d_path_used, float* d_dump, int64_t dump_cap,
+                     int64_t* d_dump_count, KArgs& A) {
     if (!ctx || !g || n_reads < 0 || path_cap < 0) return GWFA_ERR_ARG;
     if (g->device != ctx->device) return GWFA_ERR_ARG;
     int rc = check_opts(ctx, opts);
     if (rc) return rc;
-    if (n_reads == 0) return GWFA_OK;
-    if (!d_packed || !d_read_off || !d_v_start || !d_res) return GWFA_ERR_ARG;
-    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
-    HIPCHK(ctx, hipSetDevice(ctx->device));
-
+    if (n_reads > 0 && (!d_packed || !d_read_off || !d_v_start || !d_res)) return GWFA_ERR_ARG;
     if (ctx->retry_cap < n_reads) {
         for (auto& p : ctx->d_retry) { if (p) (void)hipFree(p); p = nullptr; }
         ctx->retry_cap = 0;
@@ -363,7 +361,6 @@ static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
             if (hipMalloc((void**)&p, (size_t)n_reads * 4) != hipSuccess) return GWFA_ERR_NOMEM;
         ctx->retry_cap = n_reads;
     }
-    KArgs A;
     memset(&A, 0, sizeof(A));
     A.seg = g->d_seg; A.seg_off = g->d_seg_off; A.out_off = g->d_out_off; A.out_dst = g->d_out_dst; A.n_vtx = g->n_vtx;
     A.rd = (const unsigned long long*)d_packed; A.rd_off = d_read_off; A.v_start = d_v_start;
@@ -376,21 +373,36 @@ static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     A.mlp_w = ctx->d_mlp; A.mlp_scale = ctx->d_mlp_scale;
     A.dir_factor = ctx->dir_factor;
     A.dump = d_dump; A.dump_cap = d_dump ? dump_cap : 0; A.dump_count = (unsigned long long*)d_dump_count;
+    return GWFA_OK;
+}
 
-    const int32_t* order = d_order;
-    int32_t n = n_reads;
-    HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, A.path_cursor, ctx->d_retry_count, A.dump_count, st));
-    for (int ti = 0; ti < N_TIERS; ++ti) {
-        if ((rc = ensure_tier(ctx, ti))) return rc;
-        const Tier& t = ctx->tier[ti];
-        A.order = order; A.n_reads = n; A.tier = ti;
-        A.retry = (ti + 1 < N_TIERS) ? ctx->d_retry[ti & 1] : nullptr;
-        A.arena = t.arena; A.arena_stride = t.stride;
-        A.dir_log2_max = t.dir_log2_max; A.list_cap = t.list_cap; A.cand_cap = t.cand_cap; A.sort_cap = t.sort_cap;
-        A.o_hdr = t.o_hdr; A.o_dir = t.o_dir; A.o_pages = t.o_pages; A.o_mkey = t.o_mkey;
-        A.o_tv = t.o_tv; A.o_tt = t.o_tt; A.o_lists = t.o_lists; A.o_cand = t.o_cand; A.o_sort = t.o_sort;
-        const int groups = std::min<int64_t>(t.groups, n);
-        HIPCHK(ctx, gwfa_launch_align(A, ctx->lanes, groups, st));
+// Working memory of tier ti into A; returns the workgroups to launch.
+static int set_tier(gwfa_ctx* ctx, KArgs& A, int ti, const int32_t* order, int32_t n, int* groups) {
+    int rc = ensure_tier(ctx, ti);
+    if (rc) return rc;
+    const Tier& t = ctx->tier[ti];
+    A.order = order; A.n_reads = n; A.tier = ti;
+    A.retry = (ti + 1 < N_TIERS) ? ctx->d_retry[ti & 1] : nullptr;
+    A.arena = t.arena; A.arena_stride = t.stride;
+    A.dir_log2_max = t.dir_log2_max; A.list_cap = t.list_cap; A.cand_cap = t.cand_cap; A.sort_cap = t.sort_cap;
+    A.o_hdr = t.o_hdr; A.o_dir = t.o_dir; A.o_pages = t.o_pages; A.o_mkey = t.o_mkey;
+    A.o_tv = t.o_tv; A.o_tt = t.o_tt; A.o_lists = t.o_lists; A.o_cand = t.o_cand; A.o_sort = t.o_sort;
+    *groups = (int)std::min<int64_t>(t.groups, n);
+    return GWFA_OK;
+}
+
+// Tiers ti0, ti0+1, ...: after each launch the queries that overflowed
+// their working memory (if any) are re-run on the next, larger tier.  When
+// `launched` the launch of tier ti0 has already been issued.
+static int run_tiers(gwfa_ctx* ctx, KArgs& A, int ti0, const int32_t* order, int32_t n, bool launched,
+                     hipStream_t st) {
+    for (int ti = ti0; ti < N_TIERS; ++ti) {
+        if (!(launched && ti == ti0)) {
+            int groups = 0;
+            int rc = set_tier(ctx, A, ti, order, n, &groups);
+            if (rc) return rc;
+            HIPCHK(ctx, gwfa_launch_align(A, ctx->lanes, groups, st));
+        }
         if (ti + 1 == N_TIERS) break;
         int32_t h_retry = 0;
         HIPCHK(ctx, hipMemcpyAsync(&h_retry, ctx->d_retry_count, 4, hipMemcpyDeviceToHost, st));
@@ -399,10 +411,26 @@ static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
         ctx->rerun_total += h_retry;
         order = ctx->d_retry[ti & 1];
         n = h_retry;
-        // reset the queue and the retry counter, keep the path cursor
+        // reset the queue and the retry counter, keep the path cursor and the dump counter
         HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, nullptr, ctx->d_retry_count, nullptr, st));
     }
     return GWFA_OK;
+}
+
+static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
+                     const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_order,
+                     const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
+                     int64_t* d_path_used, float* d_dump, int64_t dump_cap, int64_t* d_dump_count,
+                     void* hip_stream) {
+    if (!ctx) return GWFA_ERR_ARG;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    KArgs A;
+    int rc = fill_args(ctx, g, n_reads, d_packed, d_read_off, d_v_start, opts, d_res, d_path_buf, path_cap,
+                       d_path_used, d_dump, dump_cap, d_dump_count, A);
+    if (rc || n_reads == 0) return rc;
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, A.path_cursor, ctx->d_retry_count, A.dump_count, st));
+    return run_tiers(ctx, A, 0, d_order, n_reads, false, st);
 }
 
 int gwfa_align_batch_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
@@ -421,6 +449,85 @@ int gwfa_align_dump_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, con
     if (!d_dump || dump_cap < 0 || !d_dump_count) return GWFA_ERR_ARG;
     return align_dev(ctx, g, n_reads, d_packed, d_read_off, d_v_start, d_order, opts, d_res, d_path_buf, path_cap,
                      d_path_used, d_dump, dump_cap, d_dump_count, hip_stream);
+}
+
+struct gwfa_plan {
+    gwfa_ctx* ctx = nullptr;
+    int device = 0;
+    int64_t epoch = 0;
+    KArgs A;
+    const int32_t* order = nullptr;
+    int32_t n_reads = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+void gwfa_plan_destroy(gwfa_plan* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    delete p;
+}
+
+int gwfa_plan_create(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
+                     const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_order,
+                     const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
+                     int64_t* d_path_used, gwfa_plan** out) {
+    if (!ctx || !out || n_reads < 1) return GWFA_ERR_ARG;
+    *out = nullptr;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    gwfa_plan* p = new (std::nothrow) gwfa_plan();
+    if (!p) return GWFA_ERR_NOMEM;
+    p->ctx = ctx;
+    p->device = ctx->device;
+    p->epoch = ctx->epoch;
+    p->order = d_order;
+    p->n_reads = n_reads;
+    int rc = fill_args(ctx, g, n_reads, d_packed, d_read_off, d_v_start, opts, d_res, d_path_buf, path_cap,
+                       d_path_used, nullptr, 0, nullptr, p->A);
+    int groups = 0;
+    if (!rc) rc = set_tier(ctx, p->A, 0, d_order, n_reads, &groups);   // allocates before the capture
+    if (rc) { gwfa_plan_destroy(p); return rc; }
+    hipError_t e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        // kernels only (no memset nodes): reset of the queue and counters, then the first tier
+        hipError_t e1 = gwfa_launch_reset(ctx->d_queue, p->A.path_cursor, ctx->d_retry_count, nullptr, p->cap);
+        if (e1 == hipSuccess) e1 = gwfa_launch_align(p->A, ctx->lanes, groups, p->cap);
+        e = hipStreamEndCapture(p->cap, &p->graph);
+        if (e1 != hipSuccess) e = e1;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        rc = dev_fail(ctx, e, "plan capture");
+        gwfa_plan_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return GWFA_OK;
+}
+
+int gwfa_plan_launch(gwfa_plan* p, void* hip_stream) {
+    if (!p) return GWFA_ERR_ARG;
+    gwfa_ctx* ctx = p->ctx;
+    if (p->epoch != ctx->epoch) return GWFA_ERR_ARG;
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipGraphLaunch(p->exec, st));
+    return GWFA_OK;
+}
+
+int gwfa_plan_finish(gwfa_plan* p, void* hip_stream) {
+    if (!p) return GWFA_ERR_ARG;
+    gwfa_ctx* ctx = p->ctx;
+    if (p->epoch != ctx->epoch) return GWFA_ERR_ARG;
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    KArgs A = p->A;
+    return run_tiers(ctx, A, 0, p->order, p->n_reads, true, st);
 }
 
 int gwfa_align_batch(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint8_t* reads,

@@ -72,6 +72,11 @@ _SIGS = {
     "gwfa_label_entries": (ctypes.c_int, [_i32, _P, _P, _i64, _P, _P, _i32, _P, _P, _P, _i64, _P, _P, _P, _P,
                                           _P, _P, _P, _P, _i32]),
     "gwfa_stats": (ctypes.c_int, [_P, _P, _i32]),
+    "gwfa_plan_create": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64, _P,
+                                        ctypes.POINTER(_P)]),
+    "gwfa_plan_launch": (ctypes.c_int, [_P, _P]),
+    "gwfa_plan_finish": (ctypes.c_int, [_P, _P]),
+    "gwfa_plan_destroy": (None, [_P]),
 }
 
 MLP_N = 4801                      # parameters of the pruning network
@@ -439,3 +444,36 @@ def align_dump(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, du
     keep = final_attempt_mask(d)
     d = {k: v[keep] for k, v in d.items()}
     return res, d, produced
+
+
+class Plan:
+    """The alignment of one resident batch captured as a HIP graph
+    (gwfa_plan_*): launch() replays it on ctx's stream; finish() completes
+    any re-runs for overflowed queries (synchronising)."""
+
+    def __init__(self, ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts):
+        self.ctx, self.keep = ctx, (graph, batch, out)
+        path_cap = int(out.path.numel()) if out.path is not None else 0
+        h = _P()
+        _check(_lib.gwfa_plan_create(ctx.h, graph.h, batch.n, _tptr(batch.packed), _tptr(batch.read_off),
+                                     _tptr(batch.v_start), _tptr(batch.order), ctypes.byref(o), _tptr(out.res),
+                                     _tptr(out.path), path_cap, _tptr(out.path_used), ctypes.byref(h)),
+               "gwfa_plan_create", ctx.h)
+        self.h = h
+
+    def launch(self):
+        _check(_lib.gwfa_plan_launch(self.h, _P(self.ctx.stream.cuda_stream)), "gwfa_plan_launch", self.ctx.h)
+
+    def finish(self):
+        _check(_lib.gwfa_plan_finish(self.h, _P(self.ctx.stream.cuda_stream)), "gwfa_plan_finish", self.ctx.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.gwfa_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,9 +1,13 @@
-"""Launch-shape autotuner: lanes per query and persistent workgroups.
+"""Autotuner of the launch shape and the arena tiles: lanes per query,
+persistent workgroups, wavefront-list capacity and record-directory size and
+growth of the first working-memory tier.
 
 `autotune` times the whole batch step for each candidate on a stratified
 sample of the queries (every k-th query of the length-sorted batch, so long
-and short queries are both represented) and keeps the fastest; the result is
-cached per (device name, workload) in tune_cache.json beside this file.
+and short queries are both represented), searching one parameter at a time,
+and keeps the fastest; the result is cached per (device name, workload) in
+tune_cache.json beside this file, which `best_config` reads.
+Usage: python -m paper_2206_13574_amd.tune --workload cfg2
 """
 from __future__ import annotations
 
@@ -42,40 +46,89 @@ def best_config(workload: str) -> dict:
     return out
 
 
-def autotune(workload: str, g, r, sample: int = 4000, lanes=(64, 128, 256), groups=(0, 2048, 4096),
-             repeats: int = 2, save: bool = True, log=print) -> dict:
+def _time_config(g, sub, cfg, repeats, stream):
     from . import gwfa
     import torch
+    ctx = gwfa.Context(0, stream=stream)
+    try:
+        ctx.config(**cfg)
+        graph = gwfa.Graph.of(ctx, g)
+        with torch.cuda.stream(stream):
+            batch = gwfa.upload_reads(ctx, sub.seq, sub.off, sub.v_start)
+            out = gwfa.alloc_out(ctx, sub.n, int(sub.off[-1]) // 4 + 64 * sub.n)
+        gwfa.step_dev(ctx, graph, batch, out, gwfa.opts())     # warm-up (allocates the arenas)
+        torch.cuda.synchronize()
+        ctx.stats(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            gwfa.step_dev(ctx, graph, batch, out, gwfa.opts())
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / repeats
+        reruns = ctx.stats()["reruns"]
+        graph.close()
+    finally:
+        ctx.close()
+    return t, reruns
+
+
+# candidate values per parameter, searched one parameter at a time
+# (a first-tier arena is about 2^dir_log2_max x 640 bytes per workgroup)
+SPACE = dict(lanes=(128, 256, 512), groups=(512, 768, 0), list_cap=(1 << 13, 1 << 15, 1 << 16),
+             dir_factor=(4, 16, 64), dir_log2_max=(14, 15, 16))
+
+
+def autotune(workload: str, g, r, sample: int = 4000, repeats: int = 2, save: bool = True, rounds: int = 2,
+             space: dict = None, log=print) -> dict:
+    """Coordinate search over lanes per query, persistent workgroups and the
+    arena tiles (list capacity, directory size and growth) on a stratified
+    sample of the batch; every candidate's results must be complete (an
+    overflow re-run counts against it through its time)."""
+    import torch
+    space = space or SPACE
     lens = r.off[1:] - r.off[:-1]
     order = np.argsort(-lens, kind="stable")
     k = max(1, r.n // sample)
     sub = r.subset(order[::k][:sample])
-    best, best_t = None, float("inf")
     stream = torch.cuda.Stream()
-    for ln in lanes:
-        for gr in groups:
-            cfg = dict(DEFAULT, lanes=ln, groups=gr)
-            ctx = gwfa.Context(0, stream=stream)
-            ctx.config(**cfg)
-            graph = gwfa.Graph.of(ctx, g)
-            with torch.cuda.stream(stream):
-                batch = gwfa.upload_reads(ctx, sub.seq, sub.off, sub.v_start)
-                out = gwfa.alloc_out(ctx, sub.n, int(sub.off[-1]) // 4 + 64 * sub.n)
-            gwfa.step_dev(ctx, graph, batch, out, gwfa.opts())
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(repeats):
-                gwfa.step_dev(ctx, graph, batch, out, gwfa.opts())
-            torch.cuda.synchronize()
-            t = (time.perf_counter() - t0) / repeats
-            log(f"[tune] lanes={ln} groups={gr}: {t * 1000:.1f} ms")
-            if t < best_t:
-                best, best_t = cfg, t
-            graph.close()
-            ctx.close()
+    best = dict(DEFAULT)
+    best_t, _ = _time_config(g, sub, best, repeats, stream)
+    log(f"[tune] start {best}: {best_t * 1000:.1f} ms")
+    seen = {tuple(sorted(best.items())): best_t}
+    for rd in range(rounds):
+        changed = False
+        for key, values in space.items():
+            for v in values:
+                cfg = dict(best, **{key: v})
+                sig = tuple(sorted(cfg.items()))
+                if sig in seen:
+                    continue
+                t, reruns = _time_config(g, sub, cfg, repeats, stream)
+                seen[sig] = t
+                log(f"[tune] {key}={v}: {t * 1000:.1f} ms (re-runs {reruns})")
+                if t < best_t * 0.98:
+                    best, best_t, changed = cfg, t, True
+        if not changed:
+            break
+    log(f"[tune] best {best}: {best_t * 1000:.1f} ms")
     if save:
         c = _load()
         c[f"{_device_name()}|{workload}"] = dict(best, ms=best_t * 1000.0, sample=sub.n)
         with open(_CACHE, "w") as f:
             json.dump(c, f, indent=1, sort_keys=True)
     return best
+
+
+def main(argv=None):
+    import argparse
+    from . import synth
+    ap = argparse.ArgumentParser(description="autotune the launch shape and arena tiles for a workload")
+    ap.add_argument("--workload", default="cfg2", choices=("cfg1", "cfg2", "cfg3", "cfg4"))
+    ap.add_argument("--sample", type=int, default=4000)
+    ap.add_argument("--repeats", type=int, default=2)
+    a = ap.parse_args(argv)
+    g, r = getattr(synth, a.workload)()
+    autotune(a.workload, g, r, sample=a.sample, repeats=a.repeats, log=lambda m: print(m, flush=True))
+
+
+if __name__ == "__main__":
+    main()
