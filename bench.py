@@ -93,8 +93,7 @@ def recorded_traffic(workload: str, lanes: int):
         if not m:
             continue
         d = json.loads(m.group(1))
-        if d.get("workload") == workload and d.get("kernel_src_sha256_16") == sha and \
-                d.get("kernel", "").endswith(f"<{lanes}>"):
+        if d.get("workload") == workload and d.get("kernel_src_sha256_16") == sha and d.get("lanes") == lanes:
             return d["traffic_bytes_per_launch"], os.path.relpath(f, root)
     return None, None
 

@@ -77,18 +77,23 @@ SPACE = dict(lanes=(128, 256, 512), groups=(512, 768, 0), list_cap=(1 << 13, 1 <
              dir_factor=(4, 16, 64), dir_log2_max=(14, 15, 16))
 
 
-def autotune(workload: str, g, r, sample: int = 4000, repeats: int = 2, save: bool = True, rounds: int = 2,
+def autotune(workload: str, g, r, sample: int = 0, repeats: int = 2, save: bool = True, rounds: int = 2,
              space: dict = None, log=print) -> dict:
     """Coordinate search over lanes per query, persistent workgroups and the
     arena tiles (list capacity, directory size and growth) on a stratified
-    sample of the batch; every candidate's results must be complete (an
+    sample of the batch (sample = 0: the whole batch, which is what to tune
+    on: a sample too small to fill the GPU favours more lanes per query than
+    the full batch does); every candidate's results must be complete (an
     overflow re-run counts against it through its time)."""
     import torch
     space = space or SPACE
     lens = r.off[1:] - r.off[:-1]
     order = np.argsort(-lens, kind="stable")
-    k = max(1, r.n // sample)
-    sub = r.subset(order[::k][:sample])
+    if sample <= 0 or sample >= r.n:
+        sub = r
+    else:
+        k = max(1, r.n // sample)
+        sub = r.subset(order[::k][:sample])
     stream = torch.cuda.Stream()
     best = dict(DEFAULT)
     best_t, _ = _time_config(g, sub, best, repeats, stream)
@@ -123,7 +128,7 @@ def main(argv=None):
     from . import synth
     ap = argparse.ArgumentParser(description="autotune the launch shape and arena tiles for a workload")
     ap.add_argument("--workload", default="cfg2", choices=("cfg1", "cfg2", "cfg3", "cfg4"))
-    ap.add_argument("--sample", type=int, default=4000)
+    ap.add_argument("--sample", type=int, default=0, help="queries to time (0: all)")
     ap.add_argument("--repeats", type=int, default=2)
     a = ap.parse_args(argv)
     g, r = getattr(synth, a.workload)()
