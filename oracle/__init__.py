@@ -15,7 +15,8 @@ The arithmetic lives in ``oracle.c`` (plain C, built with gcc by
 * :func:`gwf`        -- Algorithms 1-4 (Sections 2.4-2.5), extension mode,
   optional pruning heuristic; also returns wavefront work counts.
 * :mod:`oracle.mlp_ref` -- float64 reference of the pruning MLP.
-* :mod:`oracle.labels`  -- reverse form of Eq. 1 for training labels.
+* ``orc_rev_labels`` (labels.c) -- reverse form of Eq. 1 (cost to finish
+  from a cell), the reference of the learned pruning's training labels.
 """
 from __future__ import annotations
 
