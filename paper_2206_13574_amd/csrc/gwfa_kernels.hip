@@ -358,6 +358,7 @@ __device__ __forceinline__ int32_t lower_bound_keys(const ull* keys, int32_t n, 
 // it, t only when walks are traced.
 __device__ __forceinline__ void copy_entry(const Lists& a, int32_t i, const Lists& b, int32_t j, bool w, bool t) {
     b.v[j] = a.v[i]; b.k[j] = a.k[i]; b.o[j] = a.o[i]; b.d[j] = a.d[i];
+    b.l[j] = a.l[i]; b.b[j] = a.b[i];
     if (w) b.w[j] = a.w[i];
     if (t) b.t[j] = a.t[i];
 }
@@ -504,80 +505,100 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 int adm = 0;
                 for (int32_t base = 0; base < n; base += BLOCK) {
                     const int32_t idx = base + tid;
+                    const int lane = __lane_id();
+                    const bool valid = idx < n;
                     // three fixed output slots: diagonals k-1, k, k+1
                     bool ov0 = false, ov1 = false, ov2 = false;
                     int32_t oo0 = 0, ow0 = 0, ot0 = 0, od0 = -1; bool on0 = false;
                     int32_t oo1 = 0, ow1 = 0, ot1 = 0, od1 = -1;
                     int32_t oo2 = 0, ow2 = 0, ot2 = 0, od2 = -1; bool on2 = false;
-                    int32_t v = 0, k = 0, Lv = 0;
+                    // this lane's entry (merged position idx); v = -1 past the end
+                    int32_t v = -1, k = 0, o0 = 0, ds0 = 0, W0 = 0, t0 = -1, Lv = 0;
                     int64_t sb = 0;
-                    if (idx < n) {
-                        // physical slots of merged positions idx-2 .. idx+2
-                        int32_t pa2 = idx - 2, pa1 = idx - 1, p0 = idx, pb1 = idx + 1, pb2 = idx + 2;
-                        if (vmx) {
-                            const int32_t c0 = vm_below(vmv, idx);
-                            const int32_t c1 = c0 + ((c0 < vmv.m && vmv.xpos[c0] == idx) ? 1 : 0);
-                            const int32_t c2 = c1 + ((c1 < vmv.m && vmv.xpos[c1] == idx + 1) ? 1 : 0);
-                            const int32_t cm1 = c0 - ((c0 > 0 && vmv.xpos[c0 - 1] == idx - 1) ? 1 : 0);
-                            const int32_t cm2 = cm1 - ((cm1 > 0 && vmv.xpos[cm1 - 1] == idx - 2) ? 1 : 0);
-                            p0 = vm_phys(vmv, idx, c0);
-                            pb1 = vm_phys(vmv, idx + 1, c1);
-                            pb2 = vm_phys(vmv, idx + 2, c2);
-                            pa1 = vm_phys(vmv, idx - 1, cm1);
-                            pa2 = vm_phys(vmv, idx - 2, cm2);
+                    if (valid) {
+                        const int32_t p0 = vmx ? vm_phys(vmv, idx, vm_below(vmv, idx)) : idx;
+                        v = Ls.v[p0]; k = Ls.k[p0]; o0 = Ls.o[p0]; ds0 = Ls.d[p0];
+                        Lv = Ls.l[p0]; sb = Ls.b[p0];
+                        if (q.track) W0 = Ls.w[p0];
+                        if (q.tb) t0 = Ls.t[p0];
+                    }
+                    // neighbours at merged positions idx-2 .. idx+2 are the entries of
+                    // the lanes around this one; lanes at the edge of the wave load
+                    // the ones that belong to another wave
+                    const int lm1 = lane >= 1 ? lane - 1 : lane, lm2 = lane >= 2 ? lane - 2 : lane;
+                    const int lp1 = lane <= 62 ? lane + 1 : lane, lp2 = lane <= 61 ? lane + 2 : lane;
+                    int32_t vm1 = __shfl(v, lm1, 64), km1 = __shfl(k, lm1, 64);
+                    int32_t vm2 = __shfl(v, lm2, 64), km2 = __shfl(k, lm2, 64);
+                    int32_t vp1 = __shfl(v, lp1, 64), kp1 = __shfl(k, lp1, 64), op1 = __shfl(o0, lp1, 64);
+                    int32_t dp1 = __shfl(ds0, lp1, 64);
+                    int32_t vp2 = __shfl(v, lp2, 64), kp2 = __shfl(k, lp2, 64), op2 = __shfl(o0, lp2, 64);
+                    int32_t wp1 = 0, wp2 = 0, tp1 = -1, tp2 = -1;
+                    if (q.track) { wp1 = __shfl(W0, lp1, 64); wp2 = __shfl(W0, lp2, 64); }
+                    if (q.tb) { tp1 = __shfl(t0, lp1, 64); tp2 = __shfl(t0, lp2, 64); }
+                    if (valid) {
+                        if (lane < 1) {
+                            vm1 = -1;
+                            if (idx >= 1) {
+                                const int32_t pp = vmx ? vm_phys(vmv, idx - 1, vm_below(vmv, idx - 1)) : idx - 1;
+                                vm1 = Ls.v[pp]; km1 = Ls.k[pp];
+                            }
                         }
-                        v = Ls.v[p0];
-                        k = Ls.k[p0];
-                        const int32_t o0 = Ls.o[p0], ds0 = Ls.d[p0];
-                        const int32_t W0 = q.track ? Ls.w[p0] : 0, t0 = q.tb ? Ls.t[p0] : -1;
-                        sb = seg_off[v];
-                        Lv = (int32_t)(seg_off[v + 1] - sb);
+                        if (lane < 2) {
+                            vm2 = -1;
+                            if (idx >= 2) {
+                                const int32_t pp = vmx ? vm_phys(vmv, idx - 2, vm_below(vmv, idx - 2)) : idx - 2;
+                                vm2 = Ls.v[pp]; km2 = Ls.k[pp];
+                            }
+                        }
+                        if (lane > 62) {
+                            vp1 = -1;
+                            if (idx + 1 < n) {
+                                const int32_t pp = vmx ? vm_phys(vmv, idx + 1, vm_below(vmv, idx + 1)) : idx + 1;
+                                vp1 = Ls.v[pp]; kp1 = Ls.k[pp]; op1 = Ls.o[pp]; dp1 = Ls.d[pp];
+                                if (q.track) wp1 = Ls.w[pp];
+                                if (q.tb) tp1 = Ls.t[pp];
+                            }
+                        }
+                        if (lane > 61) {
+                            vp2 = -1;
+                            if (idx + 2 < n) {
+                                const int32_t pp = vmx ? vm_phys(vmv, idx + 2, vm_below(vmv, idx + 2)) : idx + 2;
+                                vp2 = Ls.v[pp]; kp2 = Ls.k[pp]; op2 = Ls.o[pp];
+                                if (q.track) wp2 = Ls.w[pp];
+                                if (q.tb) tp2 = Ls.t[pp];
+                            }
+                        }
+                    }
+                    // candidate outputs (before the record checks) and their first
+                    // 32-base windows, fetched together with the records
+                    int32_t c0 = -1, c1 = -1, c2 = -1;    // candidate offsets, -1 = none
+                    int32_t cw1 = -1, ct1 = -1, cw2 = -1, ct2 = -1;
+                    bool rec0 = false, rec2 = false;      // needs a record check
+                    int32_t d2 = -1;
+                    int pg0 = -1, pg2 = -1;
+                    if (valid) {
                         const int32_t i0 = k + o0;
-                        // neighbours k-2, k-1, k+1, k+2 of the same vertex are
-                        // adjacent in the (merged) sorted list
-                        bool pm1 = false, pm2 = false, pp1 = false, pp2 = false;
-                        int32_t o1 = 0, W1 = 0, t1 = 0, d1 = -1, o2 = 0, W2 = 0, t2 = 0;
-                        if (idx >= 1 && Ls.v[pa1] == v) {
-                            const int32_t ka = Ls.k[pa1];
-                            if (ka == k - 1) {
-                                pm1 = true;
-                                pm2 = idx >= 2 && Ls.v[pa2] == v && Ls.k[pa2] == k - 2;
-                            } else {
-                                pm2 = ka == k - 2;
-                            }
-                        }
-                        if (idx + 1 < n && Ls.v[pb1] == v) {
-                            const int32_t kc = Ls.k[pb1];
-                            if (kc == k + 1) {
-                                pp1 = true;
-                                o1 = Ls.o[pb1]; d1 = Ls.d[pb1];
-                                W1 = q.track ? Ls.w[pb1] : 0; t1 = q.tb ? Ls.t[pb1] : -1;
-                                if (idx + 2 < n && Ls.v[pb2] == v && Ls.k[pb2] == k + 2) {
-                                    pp2 = true;
-                                    o2 = Ls.o[pb2];
-                                    W2 = q.track ? Ls.w[pb2] : 0; t2 = q.tb ? Ls.t[pb2] : -1;
-                                }
-                            } else if (kc == k + 2) {
-                                pp2 = true;
-                                o2 = Ls.o[pb1];
-                                W2 = q.track ? Ls.w[pb1] : 0; t2 = q.tb ? Ls.t[pb1] : -1;
-                            }
+                        // k-2, k-1 (k+1, k+2) of the same vertex are adjacent in the sorted list
+                        const bool pm1 = vm1 == v && km1 == k - 1;
+                        const bool pm2 = pm1 ? (vm2 == v && km2 == k - 2) : (vm1 == v && km1 == k - 2);
+                        const bool pp1 = vp1 == v && kp1 == k + 1;
+                        bool pp2;
+                        int32_t o1 = 0, W1 = 0, t1 = 0, o2 = 0, W2 = 0, t2 = 0;
+                        if (pp1) {
+                            o1 = op1; W1 = wp1; t1 = tp1; d2 = dp1;
+                            pp2 = vp2 == v && kp2 == k + 2;
+                            o2 = op2; W2 = wp2; t2 = tp2;
+                        } else {
+                            pp2 = vp1 == v && kp1 == k + 2;
+                            o2 = op1; W2 = wp1; t2 = tp1;
                         }
                         const int sl = k & 31;
                         const int32_t kp0 = k >> 5;
                         // output k-1 (this source owns it when k-1 and k-2 are absent): deletion
                         if (!pm1 && !pm2 && o0 < Lv) {
-                            const int pg = (sl > 0) ? ds0 : dir_find(q.dir, mask, dkey(v, kp0 - 1));
-                            bool rec = false;
-                            int32_t rv = 0;
-                            if (pg >= 0) {
-                                const ull w = q.pages[pg].R[(k - 1) & 31];
-                                rec = rgen(w) == q.gen;
-                                rv = rval(w);
-                            }
-                            if (!rec || o0 + 1 > rv) {
-                                ov0 = true; oo0 = o0 + 1; ow0 = W0 + 1; ot0 = t0; od0 = pg; on0 = !rec;
-                            }
+                            c0 = o0 + 1;
+                            rec0 = true;
+                            pg0 = (sl > 0) ? ds0 : dir_find(q.dir, mask, dkey(v, kp0 - 1));
                         }
                         // output k (owned when k-1 is absent): mismatch, deletion from k+1
                         if (!pm1) {
@@ -586,7 +607,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             if (pp1 && o1 < Lv && (o1 + 1 > bo || (o1 + 1 == bo && W1 + 1 > bw))) {
                                 bo = o1 + 1; bw = W1 + 1; bt = t1;
                             }
-                            if (bo > o0) { ov1 = true; oo1 = bo; ow1 = bw; ot1 = bt; od1 = ds0; }
+                            if (bo > o0) { c1 = bo; cw1 = bw; ct1 = bt; }
                         }
                         // output k+1 (always owned): insertion, mismatch at k+1, deletion from k+2
                         {
@@ -600,57 +621,67 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             }
                             if (bo >= 0) {
                                 if (pp1) {
-                                    if (bo > o1) { ov2 = true; oo2 = bo; ow2 = bw; ot2 = bt; od2 = d1; on2 = false; }
+                                    if (bo > o1) { c2 = bo; cw2 = bw; ct2 = bt; }
                                 } else {
-                                    const int pg = (sl < 31) ? ds0 : dir_find(q.dir, mask, dkey(v, kp0 + 1));
-                                    bool rec = false;
-                                    int32_t rv = 0;
-                                    if (pg >= 0) {
-                                        const ull w = q.pages[pg].R[(k + 1) & 31];
-                                        rec = rgen(w) == q.gen;
-                                        rv = rval(w);
-                                    }
-                                    if (!rec || bo > rv) { ov2 = true; oo2 = bo; ow2 = bw; ot2 = bt; od2 = pg; on2 = !rec; }
+                                    c2 = bo; cw2 = bw; ct2 = bt;
+                                    rec2 = true;
+                                    pg2 = (sl < 31) ? ds0 : dir_find(q.dir, mask, dkey(v, kp0 + 1));
                                 }
                             }
                         }
                     }
-                    // extension of the admitted outputs: the first 32-base
-                    // window of all three is fetched before any is used
+                    // records of the diagonals outside F_s (k-1, k+1) and the windows
+                    const ull rw0 = (rec0 && pg0 >= 0) ? q.pages[pg0].R[(k - 1) & 31] : 0ull;
+                    const ull rw2 = (rec2 && pg2 >= 0) ? q.pages[pg2].R[(k + 1) & 31] : 0ull;
+                    const int32_t m0 = (c0 >= 0) ? min(q.qlen - (k + c0 - 1), Lv - c0) : 0;
+                    const int32_t m1 = (c1 >= 0) ? min(q.qlen - (k + c1), Lv - c1) : 0;
+                    const int32_t m2 = (c2 >= 0) ? min(q.qlen - (k + 1 + c2), Lv - c2) : 0;
+                    const ull x0 = (m0 > 0) ? (win32(q.rd, q.q0 + k - 1 + c0) ^ win32(A.seg, sb + c0)) : 0ull;
+                    const ull x1 = (m1 > 0) ? (win32(q.rd, q.q0 + k + c1) ^ win32(A.seg, sb + c1)) : 0ull;
+                    const ull x2 = (m2 > 0) ? (win32(q.rd, q.q0 + k + 1 + c2) ^ win32(A.seg, sb + c2)) : 0ull;
+                    if (c0 >= 0) {
+                        const bool rec = rgen(rw0) == q.gen;
+                        if (!rec || c0 > rval(rw0)) {
+                            ov0 = true; oo0 = c0; ow0 = W0 + 1; ot0 = t0; od0 = pg0; on0 = !rec;
+                        }
+                    }
+                    if (c1 >= 0) { ov1 = true; oo1 = c1; ow1 = cw1; ot1 = ct1; od1 = ds0; }
+                    if (c2 >= 0) {
+                        if (!rec2) {
+                            ov2 = true; oo2 = c2; ow2 = cw2; ot2 = ct2; od2 = d2; on2 = false;
+                        } else {
+                            const bool rec = rgen(rw2) == q.gen;
+                            if (!rec || c2 > rval(rw2)) { ov2 = true; oo2 = c2; ow2 = cw2; ot2 = ct2; od2 = pg2; on2 = !rec; }
+                        }
+                    }
+                    // extension of the admitted outputs
                     int32_t lx0 = 0, lx1 = 0, lx2 = 0;
                     {
-                        const int32_t i0 = k - 1 + oo0, i1 = k + oo1, i2 = k + 1 + oo2;
-                        const int32_t m0 = ov0 ? min(q.qlen - i0, Lv - oo0) : 0;
-                        const int32_t m1 = ov1 ? min(q.qlen - i1, Lv - oo1) : 0;
-                        const int32_t m2 = ov2 ? min(q.qlen - i2, Lv - oo2) : 0;
-                        const ull x0 = (m0 > 0) ? (win32(q.rd, q.q0 + i0) ^ win32(A.seg, sb + oo0)) : 0ull;
-                        const ull x1 = (m1 > 0) ? (win32(q.rd, q.q0 + i1) ^ win32(A.seg, sb + oo1)) : 0ull;
-                        const ull x2 = (m2 > 0) ? (win32(q.rd, q.q0 + i2) ^ win32(A.seg, sb + oo2)) : 0ull;
-                        chunks += (m0 > 0) + (m1 > 0) + (m2 > 0);
-                        lx0 = x0 ? min((int32_t)(__clzll((long long)x0) >> 1), m0) : min(32, m0);
-                        lx1 = x1 ? min((int32_t)(__clzll((long long)x1) >> 1), m1) : min(32, m1);
-                        lx2 = x2 ? min((int32_t)(__clzll((long long)x2) >> 1), m2) : min(32, m2);
+                        chunks += (ov0 && m0 > 0) + (ov1 && m1 > 0) + (ov2 && m2 > 0);
+                        lx0 = ov0 ? (x0 ? min((int32_t)(__clzll((long long)x0) >> 1), m0) : min(32, m0)) : 0;
+                        lx1 = ov1 ? (x1 ? min((int32_t)(__clzll((long long)x1) >> 1), m1) : min(32, m1)) : 0;
+                        lx2 = ov2 ? (x2 ? min((int32_t)(__clzll((long long)x2) >> 1), m2) : min(32, m2)) : 0;
                         // whole windows matched and bases remain: continue
-                        if (lx0 == 32 && m0 > 32) lx0 = 32 + lcp(q.rd, q.q0 + i0 + 32, A.seg, sb + oo0 + 32, m0 - 32, chunks);
-                        if (lx1 == 32 && m1 > 32) lx1 = 32 + lcp(q.rd, q.q0 + i1 + 32, A.seg, sb + oo1 + 32, m1 - 32, chunks);
-                        if (lx2 == 32 && m2 > 32) lx2 = 32 + lcp(q.rd, q.q0 + i2 + 32, A.seg, sb + oo2 + 32, m2 - 32, chunks);
+                        if (lx0 == 32 && m0 > 32) lx0 = 32 + lcp(q.rd, q.q0 + k - 1 + oo0 + 32, A.seg, sb + oo0 + 32, m0 - 32, chunks);
+                        if (lx1 == 32 && m1 > 32) lx1 = 32 + lcp(q.rd, q.q0 + k + oo1 + 32, A.seg, sb + oo1 + 32, m1 - 32, chunks);
+                        if (lx2 == 32 && m2 > 32) lx2 = 32 + lcp(q.rd, q.q0 + k + 1 + oo2 + 32, A.seg, sb + oo2 + 32, m2 - 32, chunks);
                     }
                     const int cnt = (int)ov0 + (int)ov1 + (int)ov2;
                     int total;
                     const int pos = block_excl_scan<BLOCK>(cnt, total, S.scan);
                     adm += cnt;
                     int slot = 0;
+                    int endm = 0;        // outputs that reached the vertex end (cross every out-edge)
+                    int deg = 0;
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
                         const bool vj = (j == 0) ? ov0 : ((j == 1) ? ov1 : ov2);
-                        int ncr = 0;
-                        int32_t e0 = 0, k2 = 0, Wj = 0, tj = 0;
                         if (vj) {
                             const int32_t kj = k - 1 + j;
                             const int32_t lj = (j == 0) ? lx0 : ((j == 1) ? lx1 : lx2);
-                            int32_t o = ((j == 0) ? oo0 : ((j == 1) ? oo1 : oo2)) + lj;
-                            Wj = ((j == 0) ? ow0 : ((j == 1) ? ow1 : ow2)) + lj;
-                            tj = (j == 0) ? ot0 : ((j == 1) ? ot1 : ot2);
+                            const int32_t o = ((j == 0) ? oo0 : ((j == 1) ? oo1 : oo2)) + lj;
+                            const int32_t Wj = ((j == 0) ? ow0 : ((j == 1) ? ow1 : ow2)) + lj;
+                            const int32_t tj = (j == 0) ? ot0 : ((j == 1) ? ot1 : ot2);
                             int d = (j == 0) ? od0 : ((j == 1) ? od1 : od2);
                             const bool nw = (j == 0) ? on0 : ((j == 1) ? false : on2);
                             const int32_t p = outbase + pos + slot;
@@ -661,21 +692,38 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             } else if (d < 0) {
                                 atomicOr(&S.flags, F_GROW);
                             } else {
-                                ncr = record_entry(A, q, S, v, kj, o, Wj, d, nw, Lv);
+                                const int nc = record_entry(A, q, S, v, kj, o, Wj, d, nw, Lv);
+                                if (nc) { endm |= 1 << j; deg = nc; }
                                 Ld.v[p] = v; Ld.k[p] = kj; Ld.o[p] = o; Ld.d[p] = d;
+                                Ld.l[p] = Lv; Ld.b[p] = sb;
                                 if (q.track) Ld.w[p] = Wj;
                                 if (q.tb) Ld.t[p] = tj;
-                                e0 = out_off[v];
-                                k2 = kj + Lv;
                             }
                         }
-                        const int cp = wave_alloc(ncr, &S.ncand);
-                        for (int e = 0; e < ncr; ++e) {
-                            const int c = cp + e;
-                            if (c < A.cand_cap) {
-                                cu[c] = out_dst[e0 + e]; ck[c] = k2; cW[c] = Wj; ct[c] = tj;
-                            } else {
-                                atomicOr(&S.flags, F_LIST);
+                    }
+                    // crossing candidates of the whole wave in one allocation,
+                    // skipped when no lane of the wave reached a vertex end
+                    if (__ballot(endm != 0)) {
+                        const int ncr = __popc(endm) * deg;
+                        int cp = wave_alloc(ncr, &S.ncand);
+                        if (endm) {
+                            const int32_t e0 = out_off[v];
+#pragma unroll
+                            for (int j = 0; j < 3; ++j) {
+                                if (!((endm >> j) & 1)) continue;
+                                const int32_t lj = (j == 0) ? lx0 : ((j == 1) ? lx1 : lx2);
+                                const int32_t Wj = ((j == 0) ? ow0 : ((j == 1) ? ow1 : ow2)) + lj;
+                                const int32_t tj = (j == 0) ? ot0 : ((j == 1) ? ot1 : ot2);
+                                const int32_t k2 = k - 1 + j + Lv;
+                                for (int e = 0; e < deg; ++e) {
+                                    const int c = cp + e;
+                                    if (c < A.cand_cap) {
+                                        cu[c] = out_dst[e0 + e]; ck[c] = k2; cW[c] = Wj; ct[c] = tj;
+                                    } else {
+                                        atomicOr(&S.flags, F_LIST);
+                                    }
+                                }
+                                cp += deg;
                             }
                         }
                     }
@@ -709,18 +757,21 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         const int32_t Lv = (int32_t)(seg_off[v + 1] - sb);
                         ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, chunks);
                         Ld.o[idx] = o;
+                        Ld.l[idx] = Lv; Ld.b[idx] = sb;
                         if (q.track) Ld.w[idx] = W;
                         if (q.tb) Ld.t[idx] = t;
                         e0 = out_off[v];
                         k2 = k + Lv;
                     }
-                    const int cp = wave_alloc(ncr, &S.ncand);
-                    for (int e = 0; e < ncr; ++e) {
-                        const int c = cp + e;
-                        if (c < A.cand_cap) {
-                            cu[c] = out_dst[e0 + e]; ck[c] = k2; cW[c] = W; ct[c] = t;
-                        } else {
-                            atomicOr(&S.flags, F_LIST);
+                    if (__ballot(ncr != 0)) {
+                        const int cp = wave_alloc(ncr, &S.ncand);
+                        for (int e = 0; e < ncr; ++e) {
+                            const int c = cp + e;
+                            if (c < A.cand_cap) {
+                                cu[c] = out_dst[e0 + e]; ck[c] = k2; cW[c] = W; ct[c] = t;
+                            } else {
+                                atomicOr(&S.flags, F_LIST);
+                            }
                         }
                     }
                 }
