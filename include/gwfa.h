@@ -108,7 +108,8 @@ void gwfa_ctx_destroy(gwfa_ctx *ctx);
 
 /* Working-memory / launch configuration (used by the autotuner).
  *   lanes_per_query: 64, 128, 256 or 512 threads cooperate on one query;
- *   n_groups: persistent workgroups (0 = one per compute unit x 4);
+ *   n_groups: persistent workgroups (0 = as many as can be resident on the
+ *             device at once for the chosen lanes_per_query);
  *   dir_log2_max: log2 of the largest per-query diagonal-page directory
  *                 (each page holds 32 diagonals of one vertex; 10..22);
  *   list_cap: capacity of each per-query wavefront list (entries, even);

@@ -135,7 +135,10 @@ int ensure_tier(gwfa_ctx* ctx, int ti) {
 }
 
 void set_tiers(gwfa_ctx* ctx, int32_t dir_log2_max, int32_t list_cap) {
-    int groups = ctx->groups > 0 ? ctx->groups : ctx->n_cu * 4;
+    // default: as many persistent workgroups as can be resident at once
+    int per_cu = gwfa_align_blocks_per_cu(ctx->lanes);
+    if (per_cu <= 0) per_cu = 4;
+    int groups = ctx->groups > 0 ? ctx->groups : ctx->n_cu * per_cu;
     for (int i = 0; i < N_TIERS; ++i) {
         free_tier(ctx->tier[i]);
         Tier& t = ctx->tier[i];

@@ -45,6 +45,8 @@ struct KArgs {
 };
 
 hipError_t gwfa_launch_align(const KArgs& A, int lanes, int groups, hipStream_t st);
+// resident workgroups per compute unit of the exact alignment kernel (0 if unknown)
+int gwfa_align_blocks_per_cu(int lanes);
 hipError_t gwfa_launch_pack(const uint8_t* ascii, int64_t n, unsigned long long* out, int64_t n_words,
                             int32_t* err, hipStream_t st);
 hipError_t gwfa_launch_reset(int32_t* queue, unsigned long long* cursor, int32_t* retry_count,

@@ -266,8 +266,8 @@ __device__ __forceinline__ int32_t trace_push(const Q& q, Shared& S, int32_t v, 
 // Records an extended diagonal: its record word when it is new or reached
 // the vertex end, the end test and the pruning reductions; returns the number
 // of out-edges to cross (0 unless the vertex end was reached).
-__device__ __forceinline__ int record_entry(const KArgs& A, const Q& q, Shared& S, int32_t v, int32_t k,
-                                            int32_t o, int32_t W, int32_t d, bool mark, int32_t Lv) {
+__device__ __forceinline__ int record_entry(const Q& q, Shared& S, int32_t v, int32_t k, int32_t o, int32_t W,
+                                            int32_t d, bool mark, int32_t Lv, int32_t deg) {
     const int32_t i = k + o;
     if (mark || o == Lv) q.pages[d].R[k & 31] = mkR(q.gen, o);
     if (i == q.qlen) {
@@ -278,19 +278,19 @@ __device__ __forceinline__ int record_entry(const KArgs& A, const Q& q, Shared& 
         atomicMax(&S.amax, i + W);
         atomicMax(&S.imax, i);
     }
-    return (o == Lv) ? (A.out_off[v + 1] - A.out_off[v]) : 0;
+    return (o == Lv) ? deg : 0;
 }
 
 // Extends one admitted diagonal (Algorithm 2) and records it.
 __device__ __forceinline__ int extend_entry(const KArgs& A, const Q& q, Shared& S, int32_t v, int32_t k,
                                             int32_t& o, int32_t& W, int32_t d, bool mark, int64_t sb,
-                                            int32_t Lv, uint32_t& chunks) {
+                                            int32_t Lv, int32_t deg, uint32_t& chunks) {
     const int32_t i = k + o;
     const int32_t lim = min(q.qlen - i, Lv - o);
     const int32_t l = lcp(q.rd, q.q0 + i, A.seg, sb + o, lim, chunks);
     o += l;
     W += l;
-    return record_entry(A, q, S, v, k, o, W, d, mark, Lv);
+    return record_entry(q, S, v, k, o, W, d, mark, Lv, deg);
 }
 
 // Bitonic sort of n keys (+ payload) in place, ascending; n is a power of 2.
@@ -598,7 +598,9 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         if (!pm1 && !pm2 && o0 < Lv) {
                             c0 = o0 + 1;
                             rec0 = true;
-                            pg0 = (sl > 0) ? ds0 : dir_find(q.dir, mask, dkey(v, kp0 - 1));
+                            // a missing page means no record: the output is admitted and
+                            // needs the page, so it is created now
+                            pg0 = (sl > 0) ? ds0 : dir_insert(q.dir, mask, dkey(v, kp0 - 1), &S.dirn);
                         }
                         // output k (owned when k-1 is absent): mismatch, deletion from k+1
                         if (!pm1) {
@@ -625,13 +627,15 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                                 } else {
                                     c2 = bo; cw2 = bw; ct2 = bt;
                                     rec2 = true;
-                                    pg2 = (sl < 31) ? ds0 : dir_find(q.dir, mask, dkey(v, kp0 + 1));
+                                    pg2 = (sl < 31) ? ds0 : dir_insert(q.dir, mask, dkey(v, kp0 + 1), &S.dirn);
                                 }
                             }
                         }
                     }
                     // records of the diagonals outside F_s (k-1, k+1) and the windows
                     const ull rw0 = (rec0 && pg0 >= 0) ? q.pages[pg0].R[(k - 1) & 31] : 0ull;
+                    // first out-edge of v, needed when an output reaches the vertex end
+
                     const ull rw2 = (rec2 && pg2 >= 0) ? q.pages[pg2].R[(k + 1) & 31] : 0ull;
                     const int32_t m0 = (c0 >= 0) ? min(q.qlen - (k + c0 - 1), Lv - c0) : 0;
                     const int32_t m1 = (c1 >= 0) ? min(q.qlen - (k + c1), Lv - c1) : 0;
@@ -692,7 +696,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             } else if (d < 0) {
                                 atomicOr(&S.flags, F_GROW);
                             } else {
-                                const int nc = record_entry(A, q, S, v, kj, o, Wj, d, nw, Lv);
+                                const int nc = record_entry(q, S, v, kj, o, Wj, d, nw, Lv,
+                                                            o == Lv ? out_off[v + 1] - out_off[v] : 0);
                                 if (nc) { endm |= 1 << j; deg = nc; }
                                 Ld.v[p] = v; Ld.k[p] = kj; Ld.o[p] = o; Ld.d[p] = d;
                                 Ld.l[p] = Lv; Ld.b[p] = sb;
@@ -755,12 +760,13 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         }
                         const int64_t sb = seg_off[v];
                         const int32_t Lv = (int32_t)(seg_off[v + 1] - sb);
-                        ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, chunks);
+                        e0 = out_off[v];
+                        const int32_t deg = out_off[v + 1] - e0;
+                        ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, deg, chunks);
                         Ld.o[idx] = o;
                         Ld.l[idx] = Lv; Ld.b[idx] = sb;
                         if (q.track) Ld.w[idx] = W;
                         if (q.tb) Ld.t[idx] = t;
-                        e0 = out_off[v];
                         k2 = k + Lv;
                     }
                     if (__ballot(ncr != 0)) {
@@ -1164,6 +1170,19 @@ hipError_t gwfa_launch_align(const KArgs& A, int lanes, int groups, hipStream_t 
     }
 #undef GWFA_LAUNCH
     return hipGetLastError();
+}
+
+int gwfa_align_blocks_per_cu(int lanes) {
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (lanes) {
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<64, false>, 64, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<128, false>, 128, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<256, false>, 256, 0); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<512, false>, 512, 0); break;
+    default: break;
+    }
+    return (e == hipSuccess && nb > 0) ? nb : 0;
 }
 
 hipError_t gwfa_launch_pack(const uint8_t* ascii, int64_t n, unsigned long long* out, int64_t n_words, int32_t* err,
