@@ -1082,7 +1082,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
 }
 
 template <int BLOCK, bool LEARN>
-__global__ __launch_bounds__(BLOCK, LEARN ? 2 : 3) void k_align(KArgs A) {
+// a 512-lane workgroup fills a CU alone: it takes the whole register file instead of spilling
+__global__ __launch_bounds__(BLOCK, LEARN ? 2 : (BLOCK >= 512 ? 1 : 3)) void k_align(KArgs A) {
     __shared__ Shared S;
     char* arena = A.arena + (int64_t)blockIdx.x * A.arena_stride;
     if (LEARN && A.prune == GWFA_PRUNE_LEARNED) {
