@@ -8,14 +8,18 @@
  * each query it returns the unit-cost edit distance of Eq. 1 (Section 2.2),
  * the end position, and the vertex walk (Section 2.6, Algorithms 5-6).
  *
- * Problem form.  Extension mode: the walk starts before the first base of
- * the start vertex, the whole query is consumed, the end is free anywhere in
- * the graph.  The distance is the minimum of Eq. 1 over the last query row;
- * the end (end_v, end_off) is the lexicographically smallest cell of that
- * row holding the minimum, counting cells with end_off >= 1 plus the start
- * cell (start vertex, 0).  end_off is the number of bases of end_v consumed.
- * The global form with an end vertex (Definition 2.2 as printed) is reserved:
- * opts.end_vertex >= 0 returns GWFA_ERR_UNSUPPORTED.
+ * Problem forms.  Extension mode (opts.end_vertex = -1): the walk starts
+ * before the first base of the start vertex, the whole query is consumed,
+ * the end is free anywhere in the graph.  The distance is the minimum of
+ * Eq. 1 over the last query row; the end (end_v, end_off) is the
+ * lexicographically smallest cell of that row holding the minimum, counting
+ * cells with end_off >= 1 plus the start cell (start vertex, 0).  end_off is
+ * the number of bases of end_v consumed.
+ * Global form (Definition 2.2 as printed, Algorithm 1's end test): the walk
+ * runs from before the first base of the start vertex to the last base of an
+ * end vertex v_e; the distance is Eq. 1 at the cell (|q|, v_e, |v_e|) and
+ * the end is (v_e, |v_e|).  One end vertex for every query
+ * (opts.end_vertex >= 0) or one per query (gwfa_align_global_dev).
  *
  * Conventions for every call:
  *   - every int-returning call returns GWFA_OK (0) or a negative GWFA_ERR_*;
@@ -50,7 +54,9 @@ extern "C" {
 #define GWFA_ST_MAX_SCORE 1       /* stopped at opts.max_score without an end  */
 #define GWFA_ST_ARENA     2       /* the per-query working memory overflowed at
                                      every size tier tried                      */
-#define GWFA_ST_BAD_INPUT 3       /* start vertex out of range                  */
+#define GWFA_ST_BAD_INPUT 3       /* start (or end) vertex out of range         */
+#define GWFA_ST_UNREACHABLE 4     /* global form: no walk from the start vertex
+                                     reaches the end vertex                     */
 
 /* ---- pruning modes (gwfa_opts.prune) ----------------------------------- */
 #define GWFA_PRUNE_NONE      0    /* exact: Algorithms 1-3                      */
@@ -70,7 +76,8 @@ typedef struct {
     float keep_threshold;   /* learned: keep when the MLP logit >= keep_threshold   */
     int32_t traceback;      /* 1: fill walks (Algorithms 5-6); 0: distances only     */
     int32_t max_score;      /* -1: unbounded; else stop a query past this score     */
-    int32_t end_vertex;     /* -1: extension mode; >= 0 reserved (UNSUPPORTED)      */
+    int32_t end_vertex;     /* -1: extension mode; >= 0: global form, this end vertex
+                               for every query (GWFA_ERR_VERTEX if out of range) */
     int32_t mlp_gate;       /* learned: run the MLP only when |F_s| >= mlp_gate     */
     int32_t mlp_period;     /* learned: run the MLP every mlp_period scores (>= 1)  */
 } gwfa_opts;
@@ -175,6 +182,17 @@ int gwfa_align_batch_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, co
                          const int64_t *d_read_off, const int32_t *d_v_start, const int32_t *d_order,
                          const gwfa_opts *opts, gwfa_result *d_res, int32_t *d_path_buf, int64_t path_cap,
                          int64_t *d_path_used, void *hip_stream);
+
+/* Global form with one end vertex per query: d_v_end (device, n_reads
+ * int32).  Everything else as gwfa_align_batch_dev (opts.end_vertex must be
+ * -1).  A query whose end vertex is out of range gets GWFA_ST_BAD_INPUT; one
+ * whose end vertex cannot be reached gets GWFA_ST_UNREACHABLE (which may take
+ * as long as exploring every cell reachable from its start; opts.max_score
+ * bounds it). */
+int gwfa_align_global_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, const uint64_t *d_packed,
+                          const int64_t *d_read_off, const int32_t *d_v_start, const int32_t *d_v_end,
+                          const int32_t *d_order, const gwfa_opts *opts, gwfa_result *d_res,
+                          int32_t *d_path_buf, int64_t path_cap, int64_t *d_path_used, void *hip_stream);
 
 /* The same, also writing one trace record per wavefront entry of every
  * score that is expanded (all scores before the final one), taken after the

@@ -19,10 +19,13 @@
  *                   only cells <= D are stored.  Exact whenever d* <= D.
  *   orc_ed_global   Textbook pairwise edit distance (used to re-score walks).
  *   orc_ed_banded   The same restricted to |i-j| <= D (exact when ED <= D).
+ *   orc_dp_dense_global  The same rows; the answer is the cell
+ *                   H_{|q|, v_e, |v_e|} (the global form with an end vertex).
  *   orc_gwf         Algorithms 1-4 (Sections 2.4-2.5): the wavefront
  *                   driver, extension, expansion and the pruning heuristic,
- *                   in extension mode.  This is the oracle for the pruning
- *                   heuristic and for wavefront work counts.
+ *                   in extension mode or, with an end vertex, the global
+ *                   form.  This is the oracle for the pruning heuristic and
+ *                   for wavefront work counts.
  *   orc_rev_dp      Reverse form of Eq. 1 (cost to finish from a cell), used
  *                   to label wavefront entries for the learned pruning.
  *
@@ -151,25 +154,25 @@ static void row_answer(const ograph *g, const int32_t *h, int32_t v_s, int32_t *
 
 /* out[0]=d*, out[1]=end vertex, out[2]=end offset j, out[3]=max sweeps in a row.
  * Returns 0, or -1 on allocation failure / non-convergence. */
-int orc_dp_dense(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
-                 const int32_t *src, const int32_t *dst,
-                 const uint8_t *q, int32_t qlen, int32_t v_s, int32_t *out)
+/* Rows 0..|q| of Eq. 1; returns the last row (caller frees) or NULL. */
+static int32_t *dense_last_row(const ograph *g, const uint8_t *q, int32_t qlen, int32_t v_s, int *maxsw_out)
 {
-    ograph g;
-    if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
-    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)g.ncell);
-    int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * (size_t)g.ncell);
-    if (!prev || !cur) { free(prev); free(cur); graph_free(&g); return -1; }
+    int32_t n = g->n;
+    const uint8_t *seq = g->seq;
+    const int64_t *off = g->off;
+    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)g->ncell);
+    int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * (size_t)g->ncell);
+    if (!prev || !cur) { free(prev); free(cur); return NULL; }
     int maxsw = 0, rc = 0;
     /* row 0: initial condition H_{0,v_s,0} = 0, everything else infinite */
-    for (int64_t c = 0; c < g.ncell; c++) prev[c] = INF_H;
-    prev[g.base[v_s]] = 0;
-    int sw = row_fixpoint(&g, prev);
+    for (int64_t c = 0; c < g->ncell; c++) prev[c] = INF_H;
+    prev[g->base[v_s]] = 0;
+    int sw = row_fixpoint(g, prev);
     if (sw < 0) rc = -1; else if (sw > maxsw) maxsw = sw;
     for (int32_t i = 1; i <= qlen && rc == 0; i++) {
         uint8_t qi = up(q[i - 1]);
         for (int32_t v = 0; v < n; v++) {
-            int64_t c0 = g.base[v], L = vlen(&g, v);
+            int64_t c0 = g->base[v], L = vlen(g, v);
             const uint8_t *lab = seq + off[v];
             for (int64_t j = 0; j <= L; j++) {
                 int32_t h = prev[c0 + j] + 1;                      /* first case: consume q[i] only */
@@ -181,13 +184,48 @@ int orc_dp_dense(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
                 cur[c0 + j] = h < INF_H ? h : INF_H;
             }
         }
-        sw = row_fixpoint(&g, cur);
+        sw = row_fixpoint(g, cur);
         if (sw < 0) rc = -1; else if (sw > maxsw) maxsw = sw;
         int32_t *t = prev; prev = cur; cur = t;
     }
-    if (rc == 0) { row_answer(&g, prev, v_s, out); out[3] = maxsw; }
-    free(prev); free(cur); graph_free(&g);
-    return rc;
+    free(cur);
+    if (rc) { free(prev); return NULL; }
+    *maxsw_out = maxsw;
+    return prev;
+}
+
+int orc_dp_dense(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
+                 const int32_t *src, const int32_t *dst,
+                 const uint8_t *q, int32_t qlen, int32_t v_s, int32_t *out)
+{
+    ograph g;
+    if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
+    int maxsw = 0;
+    int32_t *last = dense_last_row(&g, q, qlen, v_s, &maxsw);
+    if (!last) { graph_free(&g); return -1; }
+    row_answer(&g, last, v_s, out);
+    out[3] = maxsw;
+    free(last); graph_free(&g);
+    return 0;
+}
+
+/* Global form of Definition 2.2: the walk runs from before the first base of
+ * v_s to the last base of v_e; the distance is H_{|q|, v_e, |v_e|} of Eq. 1
+ * (out[0]; -1 when no walk from v_s reaches v_e). */
+int orc_dp_dense_global(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
+                        const int32_t *src, const int32_t *dst,
+                        const uint8_t *q, int32_t qlen, int32_t v_s, int32_t v_e, int32_t *out)
+{
+    ograph g;
+    if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
+    int maxsw = 0;
+    int32_t *last = dense_last_row(&g, q, qlen, v_s, &maxsw);
+    if (!last) { graph_free(&g); return -1; }
+    int32_t h = last[g.base[v_e] + vlen(&g, v_e)];
+    out[0] = h >= INF_H ? -1 : h;
+    out[1] = maxsw;
+    free(last); graph_free(&g);
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -493,7 +531,7 @@ static int dq_push(dqueue *q, int32_t v, int32_t k)
  * s < counts_cap. */
 int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
             const int32_t *src, const int32_t *dst,
-            const uint8_t *q, int32_t qlen, int32_t v_s, int32_t a_diff, int32_t max_score,
+            const uint8_t *q, int32_t qlen, int32_t v_s, int32_t v_e, int32_t a_diff, int32_t max_score,
             int32_t *out, int64_t *work, int32_t *counts, int32_t counts_cap)
 {
     ograph g;
@@ -556,9 +594,18 @@ int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
         work[0] += Qn.n;
         if (counts && d < counts_cap) counts[d] = (int32_t)Qn.n;
 
+        /* ---- end test, global form (Algorithm 1 as printed): the diagonal
+         * of the end cell (v_e, |q| - |v_e|) has reached offset |v_e|.  An
+         * empty wavefront means v_e cannot be reached (out[3] = 2). */
+        if (v_e >= 0) {
+            int32_t Le = (int32_t)vlen(&g, v_e);
+            hent *e = hm_find(&H, dkey(v_e, qlen - Le));
+            if (e && e->off == Le) { out[0] = d; out[1] = v_e; out[2] = Le; break; }
+            if (Qn.n == 0) { out[3] = 2; break; }
+        }
         /* ---- end test (extension mode): some wavefront cell has consumed
          * the whole query. */
-        {
+        if (v_e < 0) {
             int found = 0; int32_t bv = -1, bj = -1;
             for (int64_t p = 0; p < Qn.n; p++) {
                 int32_t v = Qn.v[p], k = Qn.k[p];

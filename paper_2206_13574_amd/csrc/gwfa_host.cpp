@@ -335,7 +335,7 @@ int gwfa_pack_dev(gwfa_ctx* ctx, const uint8_t* d_ascii, int64_t n_bases, uint64
 
 static int check_opts(const gwfa_ctx* ctx, const gwfa_opts* o) {
     if (!o) return GWFA_ERR_ARG;
-    if (o->end_vertex >= 0) return GWFA_ERR_UNSUPPORTED;
+    if (o->end_vertex < -1) return GWFA_ERR_ARG;
     if (o->prune < 0 || o->prune > 2) return GWFA_ERR_ARG;
     if (o->prune == GWFA_PRUNE_HEURISTIC && o->a_diff < 1) return GWFA_ERR_ARG;
     if (o->prune == GWFA_PRUNE_LEARNED) {
@@ -349,13 +349,15 @@ static int check_opts(const gwfa_ctx* ctx, const gwfa_opts* o) {
 
 // Launch arguments common to every tier of one batch.
 static int fill_args(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
-                     const int64_t* d_read_off, const int32_t* d_v_start, const gwfa_opts* opts, gwfa_result* d_res,
-                     int32_t* d_path_buf, int64_t path_cap, int64_t* d_path_used, float* d_dump, int64_t dump_cap,
-                     int64_t* d_dump_count, KArgs& A) {
+                     const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_v_end,
+                     const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
+                     int64_t* d_path_used, float* d_dump, int64_t dump_cap, int64_t* d_dump_count, KArgs& A) {
     if (!ctx || !g || n_reads < 0 || path_cap < 0) return GWFA_ERR_ARG;
     if (g->device != ctx->device) return GWFA_ERR_ARG;
     int rc = check_opts(ctx, opts);
     if (rc) return rc;
+    if (opts->end_vertex >= g->n_vtx) return GWFA_ERR_VERTEX;
+    if (d_v_end && opts->end_vertex >= 0) return GWFA_ERR_ARG;
     if (n_reads > 0 && (!d_packed || !d_read_off || !d_v_start || !d_res)) return GWFA_ERR_ARG;
     if (ctx->retry_cap < n_reads) {
         for (auto& p : ctx->d_retry) { if (p) (void)hipFree(p); p = nullptr; }
@@ -367,6 +369,7 @@ static int fill_args(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     memset(&A, 0, sizeof(A));
     A.seg = g->d_seg; A.seg_off = g->d_seg_off; A.out_off = g->d_out_off; A.out_dst = g->d_out_dst; A.n_vtx = g->n_vtx;
     A.rd = (const unsigned long long*)d_packed; A.rd_off = d_read_off; A.v_start = d_v_start;
+    A.v_end = d_v_end; A.end_vertex = opts->end_vertex;
     A.res = d_res; A.path_buf = d_path_buf; A.path_cap = d_path_buf ? path_cap : 0;
     A.path_cursor = d_path_used ? (unsigned long long*)d_path_used : ctx->d_cursor;
     A.queue = ctx->d_queue; A.stats = ctx->d_stats;
@@ -421,15 +424,15 @@ static int run_tiers(gwfa_ctx* ctx, KArgs& A, int ti0, const int32_t* order, int
 }
 
 static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
-                     const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_order,
-                     const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
-                     int64_t* d_path_used, float* d_dump, int64_t dump_cap, int64_t* d_dump_count,
-                     void* hip_stream) {
+                     const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_v_end,
+                     const int32_t* d_order, const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf,
+                     int64_t path_cap, int64_t* d_path_used, float* d_dump, int64_t dump_cap,
+                     int64_t* d_dump_count, void* hip_stream) {
     if (!ctx) return GWFA_ERR_ARG;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     KArgs A;
-    int rc = fill_args(ctx, g, n_reads, d_packed, d_read_off, d_v_start, opts, d_res, d_path_buf, path_cap,
-                       d_path_used, d_dump, dump_cap, d_dump_count, A);
+    int rc = fill_args(ctx, g, n_reads, d_packed, d_read_off, d_v_start, d_v_end, opts, d_res, d_path_buf,
+                       path_cap, d_path_used, d_dump, dump_cap, d_dump_count, A);
     if (rc || n_reads == 0) return rc;
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, A.path_cursor, ctx->d_retry_count, A.dump_count, st));
@@ -440,8 +443,17 @@ int gwfa_align_batch_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, co
                          const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_order,
                          const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
                          int64_t* d_path_used, void* hip_stream) {
-    return align_dev(ctx, g, n_reads, d_packed, d_read_off, d_v_start, d_order, opts, d_res, d_path_buf, path_cap,
-                     d_path_used, nullptr, 0, nullptr, hip_stream);
+    return align_dev(ctx, g, n_reads, d_packed, d_read_off, d_v_start, nullptr, d_order, opts, d_res, d_path_buf,
+                     path_cap, d_path_used, nullptr, 0, nullptr, hip_stream);
+}
+
+int gwfa_align_global_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
+                          const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_v_end,
+                          const int32_t* d_order, const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf,
+                          int64_t path_cap, int64_t* d_path_used, void* hip_stream) {
+    if (n_reads > 0 && !d_v_end) return GWFA_ERR_ARG;
+    return align_dev(ctx, g, n_reads, d_packed, d_read_off, d_v_start, d_v_end, d_order, opts, d_res, d_path_buf,
+                     path_cap, d_path_used, nullptr, 0, nullptr, hip_stream);
 }
 
 int gwfa_align_dump_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
@@ -450,8 +462,8 @@ int gwfa_align_dump_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, con
                         int64_t* d_path_used, float* d_dump, int64_t dump_cap, int64_t* d_dump_count,
                         void* hip_stream) {
     if (!d_dump || dump_cap < 0 || !d_dump_count) return GWFA_ERR_ARG;
-    return align_dev(ctx, g, n_reads, d_packed, d_read_off, d_v_start, d_order, opts, d_res, d_path_buf, path_cap,
-                     d_path_used, d_dump, dump_cap, d_dump_count, hip_stream);
+    return align_dev(ctx, g, n_reads, d_packed, d_read_off, d_v_start, nullptr, d_order, opts, d_res, d_path_buf,
+                     path_cap, d_path_used, d_dump, dump_cap, d_dump_count, hip_stream);
 }
 
 struct gwfa_plan {
@@ -489,8 +501,8 @@ int gwfa_plan_create(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     p->epoch = ctx->epoch;
     p->order = d_order;
     p->n_reads = n_reads;
-    int rc = fill_args(ctx, g, n_reads, d_packed, d_read_off, d_v_start, opts, d_res, d_path_buf, path_cap,
-                       d_path_used, nullptr, 0, nullptr, p->A);
+    int rc = fill_args(ctx, g, n_reads, d_packed, d_read_off, d_v_start, nullptr, opts, d_res, d_path_buf,
+                       path_cap, d_path_used, nullptr, 0, nullptr, p->A);
     int groups = 0;
     if (!rc) rc = set_tier(ctx, p->A, 0, d_order, n_reads, &groups);   // allocates before the capture
     if (rc) { gwfa_plan_destroy(p); return rc; }
@@ -540,6 +552,7 @@ int gwfa_align_batch(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     int rc = check_opts(ctx, opts);
     if (rc) return rc;
     if (path_needed) *path_needed = 0;
+    if (opts->end_vertex >= g->n_vtx) return GWFA_ERR_VERTEX;
     if (n_reads == 0) return GWFA_OK;
     if (!read_off || !v_start || !res) return GWFA_ERR_ARG;
     if (read_off[0] != 0) return GWFA_ERR_ARG;

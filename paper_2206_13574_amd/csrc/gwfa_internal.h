@@ -17,6 +17,8 @@ struct KArgs {
     const int64_t* rd_off;           // n_reads+1 base offsets
     const int32_t* v_start;
     const int32_t* order;            // work-queue order or null
+    const int32_t* v_end;            // per-query end vertices (global form) or null
+    int32_t end_vertex;              // end vertex of every query (global form) or -1
     int32_t n_reads;
     // outputs (device)
     gwfa_result* res;

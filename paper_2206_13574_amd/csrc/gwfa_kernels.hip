@@ -29,8 +29,13 @@
 // open-addressing directory keyed (v, k >> 5).  A record word is
 // (generation << 32 | offset): a word whose generation is not the current
 // query's is "never seen", so pages need no initialisation.  A record holds
-// the diagonal's offset when it left the wavefront (reached the vertex end or
-// was pruned) -- the only diagonals outside F_s that can still be candidates.
+// the diagonal's offset when it left the wavefront (reached the vertex end,
+// consumed the query, or was pruned) -- the only diagonals outside F_s that
+// can still be candidates.
+//
+// Global form (an end vertex v_e): the end test is Algorithm 1's, the cell
+// (|q|, v_e, |v_e|); diagonals that consumed the query go on by deletions
+// and crossings; an empty wavefront means v_e cannot be reached.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -79,26 +84,37 @@ __device__ __forceinline__ ull win32(const ull* __restrict__ w, int64_t p) {
 }
 
 // LCP of q[qp ...] and label[sp ...], at most lim bases.  Each step
-// compares up to four 32-base windows whose loads are issued together, so a
-// long exact run costs one memory round trip per 128 bases.  Windows that
-// start at or past lim are not loaded (both stores end with two words of
-// padding, so a window starting inside the range stays in bounds).
+// compares up to four consecutive 32-base windows; they share words (window j
+// spans words j and j+1 of the step), so a step loads at most five words per
+// sequence, all issued together: a long exact run costs one memory round trip
+// per 128 bases.  Words past the range are not loaded (both stores end with
+// two words of padding, so a window starting inside the range stays in
+// bounds).
 __device__ __forceinline__ int32_t lcp(const ull* __restrict__ qw, int64_t qp, const ull* __restrict__ sw,
                                        int64_t sp, int32_t lim, uint32_t& chunks) {
     int32_t l = 0;
+    const int qs = (int)((qp & 31) * 2), ss = (int)((sp & 31) * 2);
     while (l < lim) {
         const int32_t rem = lim - l;
-        ull x[4];
+        const int64_t qi = (qp + l) >> 5, si = (sp + l) >> 5;
+        ull a[5], b[5];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            x[j] = (32 * j < rem) ? (win32(qw, qp + l + 32 * j) ^ win32(sw, sp + l + 32 * j)) : 0ull;
+        for (int j = 0; j < 5; ++j) {
+            // word j is needed by windows j-1 and j
+            const bool need = 32 * (j - 1) < rem;
+            a[j] = need ? qw[qi + j] : 0ull;
+            b[j] = need ? sw[si + j] : 0ull;
+        }
         int32_t m = 0;
         bool stop = false;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (!stop && 32 * j < rem) {
                 ++chunks;
-                if (x[j]) { m += (int32_t)(__clzll((long long)x[j]) >> 1); stop = true; }
+                const ull xq = (a[j] << qs) | ((a[j + 1] >> 1) >> (63 - qs));
+                const ull xs = (b[j] << ss) | ((b[j + 1] >> 1) >> (63 - ss));
+                const ull x = xq ^ xs;
+                if (x) { m += (int32_t)(__clzll((long long)x) >> 1); stop = true; }
                 else m += 32;
             }
         }
@@ -177,7 +193,7 @@ __device__ __forceinline__ int block_excl_scan(int x, int& total, int* scan) {
     int wt;
     const int ex = wave_excl_scan(x, wt);
     const int w = threadIdx.x >> 6;
-    if (NW == 1) { total = wt; return ex; }
+    if (NW == 1) { total = __builtin_amdgcn_readfirstlane(wt); return ex; }
     if (__lane_id() == 0) scan[w] = wt;
     lds_barrier();
     int off = 0, tot = 0;
@@ -188,7 +204,7 @@ __device__ __forceinline__ int block_excl_scan(int x, int& total, int* scan) {
         tot += y;
     }
     lds_barrier();
-    total = tot;
+    total = __builtin_amdgcn_readfirstlane(tot);   // block-uniform: kept in a scalar register
     return off + ex;
 }
 
@@ -199,7 +215,7 @@ __device__ __forceinline__ int read_uniform(const int& x) {
     __syncthreads();
     const int v = *(const volatile int*)&x;
     __syncthreads();
-    return v;
+    return __builtin_amdgcn_readfirstlane(v);
 }
 
 // A wavefront list: per entry the diagonal (v, k), its offset o, walk length
@@ -242,6 +258,7 @@ struct Q {
     const ull* rd;
     int64_t q0;
     int32_t qlen, vs;
+    int32_t ve;       // end vertex (global form) or -1 (extension mode)
     ull* dir;
     Page* pages;
     ull* mkey;
@@ -269,10 +286,15 @@ __device__ __forceinline__ int32_t trace_push(const Q& q, Shared& S, int32_t v, 
 __device__ __forceinline__ int record_entry(const Q& q, Shared& S, int32_t v, int32_t k, int32_t o, int32_t W,
                                             int32_t d, bool mark, int32_t Lv, int32_t deg) {
     const int32_t i = k + o;
-    if (mark || o == Lv) q.pages[d].R[k & 31] = mkR(q.gen, o);
-    if (i == q.qlen) {
+    // the record is written when the diagonal is new or may leave the
+    // wavefront: at the vertex end, or with the query consumed (no mismatch
+    // can advance it; in the global form the search goes on past i = |q|)
+    if (mark || o == Lv || i == q.qlen) q.pages[d].R[k & 31] = mkR(q.gen, o);
+    // end test: extension mode, any cell of the last query row; global form,
+    // the cell at the end of the end vertex (Algorithm 1)
+    if (i == q.qlen && (q.ve < 0 || (v == q.ve && o == Lv))) {
         S.found = 1;
-        if (o >= 1 || v == q.vs) atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
+        if (q.ve >= 0 || o >= 1 || v == q.vs) atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
     }
     if (q.track) {
         atomicMax(&S.amax, i + W);
@@ -393,17 +415,22 @@ __device__ __forceinline__ void entry_features(float* f, int32_t s, int32_t i, i
     f[7] = log1pf((float)(qlen - i));
 }
 
-template <int BLOCK, bool LEARN>
+// MODE 0: exact; 1: walk lengths tracked (Algorithm 4); 2: learned keep/drop
+// or trace dump.  Each mode is its own instantiation so that the registers of
+// what it does not use are not allocated.
+template <int BLOCK, int MODE>
 __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shared& S) {
+    constexpr bool LEARN = MODE == 2;
     const int tid = threadIdx.x;
     Q q;
     q.rd = A.rd;
     q.q0 = A.rd_off[r];
     q.qlen = (int32_t)(A.rd_off[r + 1] - q.q0);
     q.vs = A.v_start[r];
+    q.ve = A.v_end ? A.v_end[r] : A.end_vertex;
     gwfa_result* out = A.res + r;
     const int64_t t_begin = (int64_t)wall_clock64();
-    if (q.vs < 0 || q.vs >= A.n_vtx) {
+    if (q.vs < 0 || q.vs >= A.n_vtx || q.ve < -1 || q.ve >= A.n_vtx || (A.v_end && q.ve < 0)) {
         if (tid == 0) {
             out->t_begin = t_begin; out->t_end = t_begin;
             out->dist = -1; out->end_v = -1; out->end_off = -1; out->status = GWFA_ST_BAD_INPUT;
@@ -420,7 +447,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     q.Tv = reinterpret_cast<int32_t*>(arena + A.o_tv);
     q.Tt = reinterpret_cast<int32_t*>(arena + A.o_tt);
     q.tb = A.traceback != 0;
-    q.track = A.prune != GWFA_PRUNE_NONE || A.dump != nullptr;
+    q.track = MODE >= 1;   // the launch picks MODE >= 1 when pruning or dumping
     uint32_t* hdr = reinterpret_cast<uint32_t*>(arena + A.o_hdr);
     int32_t* const lbase = reinterpret_cast<int32_t*>(arena + A.o_lists);
     const int64_t lcap = A.list_cap;
@@ -469,7 +496,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             S.tick[0] = S.tick[1] = S.tick[2] = S.tick[3] = 0;
         }
         __syncthreads();
-        q.gen = S.gen;
+        q.gen = __builtin_amdgcn_readfirstlane(S.gen);
         if (tid == 0) {   // score 0 starts from the start diagonal (v_s, 0) at offset 0
             const int ds = dir_insert(q.dir, mask, dkey(q.vs, 0), &S.dirn);
             const int32_t t0 = q.tb ? trace_push(q, S, q.vs, -1) : -1;
@@ -665,10 +692,18 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         lx0 = ov0 ? (x0 ? min((int32_t)(__clzll((long long)x0) >> 1), m0) : min(32, m0)) : 0;
                         lx1 = ov1 ? (x1 ? min((int32_t)(__clzll((long long)x1) >> 1), m1) : min(32, m1)) : 0;
                         lx2 = ov2 ? (x2 ? min((int32_t)(__clzll((long long)x2) >> 1), m2) : min(32, m2)) : 0;
-                        // whole windows matched and bases remain: continue
-                        if (lx0 == 32 && m0 > 32) lx0 = 32 + lcp(q.rd, q.q0 + k - 1 + oo0 + 32, A.seg, sb + oo0 + 32, m0 - 32, chunks);
-                        if (lx1 == 32 && m1 > 32) lx1 = 32 + lcp(q.rd, q.q0 + k + oo1 + 32, A.seg, sb + oo1 + 32, m1 - 32, chunks);
-                        if (lx2 == 32 && m2 > 32) lx2 = 32 + lcp(q.rd, q.q0 + k + 1 + oo2 + 32, A.seg, sb + oo2 + 32, m2 - 32, chunks);
+                        // whole windows matched and bases remain: continue (one call
+                        // site for the three outputs keeps the register demand down)
+#pragma unroll 1
+                        for (int j = 0; j < 3; ++j) {
+                            const int32_t lj = (j == 0) ? lx0 : ((j == 1) ? lx1 : lx2);
+                            const int32_t mj = (j == 0) ? m0 : ((j == 1) ? m1 : m2);
+                            if (lj == 32 && mj > 32) {
+                                const int32_t oj = (j == 0) ? oo0 : ((j == 1) ? oo1 : oo2);
+                                const int32_t r = 32 + lcp(q.rd, q.q0 + k - 1 + j + oj + 32, A.seg, sb + oj + 32, mj - 32, chunks);
+                                if (j == 0) lx0 = r; else if (j == 1) lx1 = r; else lx2 = r;
+                            }
+                        }
                     }
                     const int cnt = (int)ov0 + (int)ov1 + (int)ov2;
                     int total;
@@ -782,8 +817,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     }
                 }
                 __syncthreads();
-                const int32_t nc = S.ncand;
-                const int f1 = S.flags | ((S.dirn > half || S.mn > half) ? F_GROW : 0);
+                const int32_t nc = __builtin_amdgcn_readfirstlane(S.ncand);
+                const int f1 = __builtin_amdgcn_readfirstlane(S.flags | ((S.dirn > half || S.mn > half) ? F_GROW : 0));
                 __syncthreads();
                 if (tid == 0) S.ncand = 0;
                 if (f1) { rflags = f1; restart = true; break; }
@@ -825,8 +860,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     }
                 }
                 __syncthreads();
-                const int32_t xn = S.n_out;
-                const int f2 = S.flags | ((S.dirn > half) ? F_GROW : 0);
+                const int32_t xn = __builtin_amdgcn_readfirstlane(S.n_out);
+                const int f2 = __builtin_amdgcn_readfirstlane(S.flags | ((S.dirn > half) ? F_GROW : 0));
                 __syncthreads();
                 if (f2) { rflags = f2; restart = true; break; }
                 xlo = xhi;
@@ -838,9 +873,9 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             const int32_t ntot = xhi;
             work += ntot;
             __syncthreads();
-            const int found = S.found;
-            const int32_t amax = S.amax;
-            const int32_t imax = S.imax;
+            const int found = __builtin_amdgcn_readfirstlane(S.found);
+            const int32_t amax = __builtin_amdgcn_readfirstlane(S.amax);
+            const int32_t imax = __builtin_amdgcn_readfirstlane(S.imax);
             __syncthreads();
             // ========== end test (extension mode) ==========
             if (found) {
@@ -856,9 +891,12 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 break;
             }
             if (A.max_score >= 0 && s >= A.max_score) { status = GWFA_ST_MAX_SCORE; break; }
-            // cannot happen for valid input (the query can always be
-            // inserted); a guard so that every workgroup finishes
-            if (ntot == 0 || s > q.qlen + 1) { status = GWFA_ST_MAX_SCORE; break; }
+            // global form: an empty wavefront means the end vertex cannot be
+            // reached.  Extension mode: cannot happen for valid input (the
+            // query can always be inserted); a guard so that every workgroup
+            // finishes.
+            if (ntot == 0) { status = q.ve >= 0 ? GWFA_ST_UNREACHABLE : GWFA_ST_MAX_SCORE; break; }
+            if (q.ve < 0 && s > q.qlen + 1) { status = GWFA_ST_MAX_SCORE; break; }
             // ========== merge the crossing diagonals into the sorted list ==========
             // Small sets (<= XS_LDS) are merged virtually: their keys are sorted
             // in LDS and each gets its merged position (its rank among the
@@ -921,7 +959,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             if (tid == 0) { const ull t2 = wall_clock64(); S.tick[2] += t2 - tk; tk = t2; }
             n_cur = ntot;
             // ========== pruning (Algorithm 4) ==========
-            if (A.prune == GWFA_PRUNE_HEURISTIC && amax > A.a_diff) {
+            if (MODE >= 1 && A.prune == GWFA_PRUNE_HEURISTIC && amax > A.a_diff) {
                 const Lists Ls = LL(cur);
                 const Lists Lp = LL(1 - cur);
                 VMerge vmv;
@@ -1081,9 +1119,10 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     __syncthreads();
 }
 
-template <int BLOCK, bool LEARN>
 // a 512-lane workgroup fills a CU alone: it takes the whole register file instead of spilling
-__global__ __launch_bounds__(BLOCK, LEARN ? 2 : (BLOCK >= 512 ? 1 : 3)) void k_align(KArgs A) {
+template <int BLOCK, int MODE>
+__global__ __launch_bounds__(BLOCK, MODE == 2 ? 2 : (BLOCK >= 512 ? 1 : 3)) void k_align(KArgs A) {
+    constexpr bool LEARN = MODE == 2;
     __shared__ Shared S;
     char* arena = A.arena + (int64_t)blockIdx.x * A.arena_stride;
     if (LEARN && A.prune == GWFA_PRUNE_LEARNED) {
@@ -1094,11 +1133,11 @@ __global__ __launch_bounds__(BLOCK, LEARN ? 2 : (BLOCK >= 512 ? 1 : 3)) void k_a
     for (;;) {
         if (threadIdx.x == 0) S.read = atomicAdd(A.queue, 1);
         __syncthreads();
-        const int ridx = S.read;
+        const int ridx = __builtin_amdgcn_readfirstlane(S.read);
         __syncthreads();
         if (ridx >= A.n_reads) break;
         const int r = A.order ? A.order[ridx] : ridx;
-        align_read<BLOCK, LEARN>(A, arena, r, S);
+        align_read<BLOCK, MODE>(A, arena, r, S);
     }
 }
 
@@ -1157,11 +1196,12 @@ __global__ void k_reset(int32_t* queue, ull* path_cursor, int32_t* retry_count, 
 // ---------------------------------------------------------------------------
 hipError_t gwfa_launch_align(const KArgs& A, int lanes, int groups, hipStream_t st) {
     // the learned keep/drop and the trace dump live in their own instantiation
-    const bool learn = A.prune == GWFA_PRUNE_LEARNED || A.dump != nullptr;
+    const int mode = (A.prune == GWFA_PRUNE_LEARNED || A.dump != nullptr) ? 2 : (A.prune != GWFA_PRUNE_NONE ? 1 : 0);
     (void)hipGetLastError();   // the launch status below must not report an older, unrelated error
 #define GWFA_LAUNCH(L)                                                                                     \
-    if (learn) hipLaunchKernelGGL((gwfa_dev::k_align<L, true>), dim3(groups), dim3(L), 0, st, A);          \
-    else hipLaunchKernelGGL((gwfa_dev::k_align<L, false>), dim3(groups), dim3(L), 0, st, A);
+    if (mode == 2) hipLaunchKernelGGL((gwfa_dev::k_align<L, 2>), dim3(groups), dim3(L), 0, st, A);        \
+    else if (mode == 1) hipLaunchKernelGGL((gwfa_dev::k_align<L, 1>), dim3(groups), dim3(L), 0, st, A);   \
+    else hipLaunchKernelGGL((gwfa_dev::k_align<L, 0>), dim3(groups), dim3(L), 0, st, A);
     switch (lanes) {
     case 64: GWFA_LAUNCH(64) break;
     case 128: GWFA_LAUNCH(128) break;
@@ -1177,10 +1217,10 @@ int gwfa_align_blocks_per_cu(int lanes) {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (lanes) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<64, false>, 64, 0); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<128, false>, 128, 0); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<256, false>, 256, 0); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<512, false>, 512, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<64, 0>, 64, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<128, 0>, 128, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<256, 0>, 256, 0); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gwfa_dev::k_align<512, 0>, 512, 0); break;
     default: break;
     }
     return (e == hipSuccess && nb > 0) ? nb : 0;

@@ -29,7 +29,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK = 0
 ERR_ARG, ERR_VERTEX, ERR_ALPHABET, ERR_EMPTY_LABEL = -1, -2, -3, -4
 ERR_NOMEM, ERR_DEVICE, ERR_PATH_CAP, ERR_UNSUPPORTED = -5, -6, -7, -8
-ST_OK, ST_MAX_SCORE, ST_ARENA, ST_BAD_INPUT = 0, 1, 2, 3
+ST_OK, ST_MAX_SCORE, ST_ARENA, ST_BAD_INPUT, ST_UNREACHABLE = 0, 1, 2, 3, 4
 PRUNE_NONE, PRUNE_HEURISTIC, PRUNE_LEARNED = 0, 1, 2
 
 RESULT_DTYPE = np.dtype([("dist", "<i4"), ("end_v", "<i4"), ("end_off", "<i4"), ("status", "<i4"),
@@ -61,6 +61,8 @@ _SIGS = {
     "gwfa_align_batch": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64, _P]),
     "gwfa_align_batch_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
                                             _P, _P]),
+    "gwfa_align_global_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
+                                             _P, _P]),
     "gwfa_align_dump_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
                                            _P, _P, _i64, _P, _P]),
     "gwfa_mlp_load": (ctypes.c_int, [_P, _P, _i64, _P]),
@@ -258,19 +260,27 @@ def pack_dev(ctx: Context, batch: DeviceBatch, err) -> None:
                               _P(ctx.stream.cuda_stream)), "gwfa_pack_dev", ctx.h)
 
 
-def align_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts) -> None:
-    """Aligns a device-resident batch (already packed) on ctx's stream."""
+def align_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts, v_end=None) -> None:
+    """Aligns a device-resident batch (already packed) on ctx's stream.
+    v_end: optional int32 device tensor of per-query end vertices (global
+    form, gwfa_align_global_dev)."""
     path_cap = int(out.path.numel()) if out.path is not None else 0
+    if v_end is not None:
+        _check(_lib.gwfa_align_global_dev(ctx.h, graph.h, batch.n, _tptr(batch.packed), _tptr(batch.read_off),
+                                          _tptr(batch.v_start), _tptr(v_end), _tptr(batch.order), ctypes.byref(o),
+                                          _tptr(out.res), _tptr(out.path), path_cap, _tptr(out.path_used),
+                                          _P(ctx.stream.cuda_stream)), "gwfa_align_global_dev", ctx.h)
+        return
     _check(_lib.gwfa_align_batch_dev(ctx.h, graph.h, batch.n, _tptr(batch.packed), _tptr(batch.read_off),
                                      _tptr(batch.v_start), _tptr(batch.order), ctypes.byref(o), _tptr(out.res),
                                      _tptr(out.path), path_cap, _tptr(out.path_used),
                                      _P(ctx.stream.cuda_stream)), "gwfa_align_batch_dev", ctx.h)
 
 
-def step_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts) -> None:
+def step_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts, v_end=None) -> None:
     """One pass of the whole path on resident queries: pack, then align."""
     pack_dev(ctx, batch, out.err)
-    align_dev(ctx, graph, batch, out, o)
+    align_dev(ctx, graph, batch, out, o, v_end)
 
 
 def fetch(out: DeviceOut, n: int):
@@ -281,10 +291,11 @@ def fetch(out: DeviceOut, n: int):
     return res, path, used
 
 
-def align(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_cap: int = None):
+def align(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_cap: int = None, v_end=None):
     """Convenience: host queries in, results out (through the device-side
-    entry points).  Returns (results, paths) with paths a list of int32
-    arrays (or None when traceback is off)."""
+    entry points).  v_end: optional per-query end vertices (global form).
+    Returns (results, paths) with paths a list of int32 arrays (or None when
+    traceback is off)."""
     if o is None:
         o = opts()
     seq = np.ascontiguousarray(np.frombuffer(seq, dtype=np.uint8) if isinstance(seq, (bytes, bytearray)) else seq,
@@ -295,7 +306,11 @@ def align(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_ca
     if path_cap is None:
         path_cap = (int(off[-1]) + 64 * n) if o.traceback else 0
     out = alloc_out(ctx, n, path_cap)
-    step_dev(ctx, graph, batch, out, o)
+    ve = None
+    if v_end is not None:
+        ve = ctx.torch.from_numpy(np.ascontiguousarray(v_end, dtype=np.int32) if n else
+                                  np.zeros(1, np.int32)).to(ctx.tdev)
+    step_dev(ctx, graph, batch, out, o, ve)
     ctx.torch.cuda.synchronize(ctx.tdev)
     if int(out.err.cpu().item()) != 0:
         raise GwfaError(ERR_ALPHABET, "gwfa_pack_dev")

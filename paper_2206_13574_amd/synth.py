@@ -71,6 +71,8 @@ class Reads:
     n_edits: np.ndarray      # int32 injected edits (upper bound on the distance)
     err_rate: np.ndarray     # float64 per-read error rate
     meta: dict = field(default_factory=dict)
+    v_end: np.ndarray = None     # int32 last vertex of each generating walk (global-form end vertex)
+    end_rest: np.ndarray = None  # int32 bases of v_end after the read's last spelled base
 
     @property
     def n(self) -> int:
@@ -87,7 +89,9 @@ class Reads:
         seq = np.concatenate([self.seq[self.off[r]:self.off[r + 1]] for r in idx]) if len(idx) else \
             np.zeros(0, dtype=np.uint8)
         return Reads(seq, off, self.v_start[idx].copy(), self.n_edits[idx].copy(),
-                     self.err_rate[idx].copy(), dict(self.meta))
+                     self.err_rate[idx].copy(), dict(self.meta),
+                     None if self.v_end is None else self.v_end[idx].copy(),
+                     None if self.end_rest is None else self.end_rest[idx].copy())
 
 
 def _gaps(rng, mean, n_max, lo=2):
@@ -310,6 +314,11 @@ def sample_reads(g: Graph, seed: int, n_reads: int, length, err, laps=(1, 1),
     if len(todo):
         raise RuntimeError(f"could not place {len(todo)} reads of the requested length")
 
+    # last vertex of each generating walk (the end vertex of a global-form
+    # alignment of the read) and the bases of it the read does not spell
+    v_end = np.array([int(walks[r][0][-1]) for r in range(n_reads)], dtype=np.int32)
+    end_rest = np.array([int(lab_len[walks[r][0][-1]] - walks[r][1][-1]) for r in range(n_reads)], dtype=np.int32)
+
     # spell, then inject errors, in chunks of reads
     out_seqs, n_edits = [], np.zeros(n_reads, dtype=np.int32)
     for c0 in range(0, n_reads, chunk):
@@ -346,7 +355,7 @@ def sample_reads(g: Graph, seed: int, n_reads: int, length, err, laps=(1, 1),
     off = np.zeros(n_reads + 1, dtype=np.int64)
     off[1:] = np.cumsum(lens)
     return Reads(seq, off, starts.astype(np.int32), n_edits, E,
-                 meta=dict(seed=seed, n_reads=n_reads, laps=laps))
+                 meta=dict(seed=seed, n_reads=n_reads, laps=laps), v_end=v_end, end_rest=end_rest)
 
 
 # --------------------------------------------------------------------------

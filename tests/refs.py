@@ -143,3 +143,54 @@ def spell_random_walk(rng, labels, edges, v_s, max_len):
         v = succ[v][int(rng.integers(0, len(succ[v])))]
         walk.append(v)
     return "".join(out).encode(), walk
+
+
+def brute_force_global(labels, edges, q: bytes, v_s: int, v_e: int) -> int:
+    """Global form with an end vertex: min over every walk from v_s to v_e of
+    the edit distance between q and the walk's whole spelled string; -1 when
+    v_e cannot be reached.  Walks longer than |q| + max(|q|, |S|) bases, S the
+    shortest walk, cannot be optimal (their cost exceeds S's), which bounds
+    the enumeration on cyclic graphs."""
+    import heapq
+    q = (q.decode() if isinstance(q, (bytes, bytearray)) else q).upper()
+    n = len(q)
+    succ = {}
+    for a, b in edges:
+        succ.setdefault(a, []).append(b)
+    # shortest spelled length of a walk v_s ... v_e (whole labels)
+    dist = {v_s: len(labels[v_s])}
+    pq = [(len(labels[v_s]), v_s)]
+    while pq:
+        d, v = heapq.heappop(pq)
+        if d > dist.get(v, 1 << 60):
+            continue
+        for u in succ.get(v, []):
+            nd = d + len(labels[u])
+            if nd < dist.get(u, 1 << 60):
+                dist[u] = nd
+                heapq.heappush(pq, (nd, u))
+    if v_e not in dist:
+        return -1
+    limit = n + max(n, dist[v_e])
+    best = [1 << 60]
+    qa = list(q)
+
+    def step(col, c):
+        new = [col[0] + 1]
+        for i in range(1, n + 1):
+            new.append(min(col[i - 1] + (qa[i - 1] != c), col[i] + 1, new[i - 1] + 1))
+        return new
+
+    def dfs(v, col, depth):
+        for ch in labels[v].upper():
+            col = step(col, ch)
+            depth += 1
+            if depth > limit or min(col) >= best[0]:
+                return
+        if v == v_e and col[n] < best[0]:
+            best[0] = col[n]
+        for u in succ.get(v, []):
+            dfs(u, col, depth)
+
+    dfs(v_s, list(range(n + 1)), 0)
+    return best[0]

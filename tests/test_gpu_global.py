@@ -1,0 +1,109 @@
+"""GPU parity of the global form (Definition 2.2 with an end vertex,
+Algorithm 1's end test) through the C ABI: distances against the dense
+global oracle, work counts against the Algorithms 1-4 transcription run in
+the global form, unreachable end vertices, walks re-scored over the whole
+spelled walk."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2206_13574_amd import synth
+from tests import refs
+from tests.test_gpu_parity import union_graph, reads_of
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-global] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def G(gpu_lib):
+    ctx = gpu_lib.Context(0)
+    yield gpu_lib, ctx
+    ctx.close()
+
+
+def _run(gw, ctx, g, qs, vs, ve, o=None):
+    graph = gw.Graph.of(ctx, g)
+    try:
+        seq, off = reads_of(qs)
+        return gw.align(ctx, graph, seq, off, np.asarray(vs, dtype=np.int32), o, v_end=np.asarray(ve, dtype=np.int32),
+                        path_cap=int(off[-1]) * 4 + 256 * len(qs))
+    finally:
+        graph.close()
+
+
+def _check_walk(g, q, v_s, v_e, d, path):
+    assert path is not None and path[0] == v_s and path[-1] == v_e and O.is_walk(g, path)
+    Le = int(g.seg_off[v_e + 1] - g.seg_off[v_e])
+    assert O.ed_global(q, O.spell_walk(g, path, Le)) == d
+
+
+def test_global_tiny_random_graphs(G):
+    gw, ctx = G
+    rng = np.random.default_rng(9301)
+    cases = []
+    for _ in range(2000):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(1, 7)), max_label=5, p_edge=0.35,
+                                                qlen=int(rng.integers(0, 30)))
+        cases.append((labels, edges, q, vs, int(rng.integers(0, len(labels)))))
+    g, base = union_graph([c[:4] for c in cases])
+    say(f"{len(cases)} tiny graphs, one launch")
+    res, paths = _run(gw, ctx, g, [c[2] for c in cases], [c[3] + b for c, b in zip(cases, base)],
+                      [c[4] + b for c, b in zip(cases, base)])
+    n_unreach = 0
+    for i, (labels, edges, q, vs, ve) in enumerate(cases):
+        d = O.dp_dense_global((labels, edges), q, vs, ve)
+        if d < 0:
+            n_unreach += 1
+            assert res[i]["status"] == gw.ST_UNREACHABLE and res[i]["dist"] == -1, i
+            continue
+        wf = O.gwf((labels, edges), q, vs, v_e=ve)
+        r = res[i]
+        assert (r["status"], r["dist"], r["end_v"] - base[i], r["end_off"], r["work"]) == \
+            (0, d, ve, len(labels[ve]), wf["work"]), (i, labels, edges, q, vs, ve)
+        _check_walk(g, q, vs + base[i], ve + base[i], d, paths[i])
+    assert 100 < n_unreach < len(cases) - 500
+
+
+def test_global_cfg1_reads_to_their_walk_end(G):
+    gw, ctx = G
+    g, r = synth.cfg1()
+    qs = [r.read(i) for i in range(r.n)]
+    say("cfg1, exact and Algorithm 4")
+    res, paths = _run(gw, ctx, g, qs, r.v_start, r.v_end)
+    for i in range(r.n):
+        d = O.dp_dense_global(g, qs[i], int(r.v_start[i]), int(r.v_end[i]))
+        assert res[i]["status"] == 0 and res[i]["dist"] == d <= r.n_edits[i] + r.end_rest[i]
+        assert res[i]["work"] == O.gwf(g, qs[i], int(r.v_start[i]), v_e=int(r.v_end[i]))["work"]
+        _check_walk(g, qs[i], int(r.v_start[i]), int(r.v_end[i]), d, paths[i])
+    for a in (8, 30):
+        res2, _ = _run(gw, ctx, g, qs, r.v_start, r.v_end, gw.opts(prune=gw.PRUNE_HEURISTIC, a_diff=a))
+        for i in range(r.n):
+            ref = O.gwf(g, qs[i], int(r.v_start[i]), a_diff=a, v_e=int(r.v_end[i]))
+            assert (res2[i]["dist"], res2[i]["work"]) == (ref["dist"], ref["work"]), (i, a)
+            assert res2[i]["dist"] >= res[i]["dist"]
+
+
+def test_global_shared_end_vertex_and_errors(G):
+    gw, ctx = G
+    g = synth.Graph.from_labels(["ACGT", "TT", "GA"], [(0, 1), (1, 2), (2, 1)])
+    graph = gw.Graph.of(ctx, g)
+    say("shared end vertex (opts.end_vertex), errors")
+    seq, off = reads_of([b"ACGTTT", b"ACGTTTGATT", b""])
+    res, paths = gw.align(ctx, graph, seq, off, np.zeros(3, np.int32), gw.opts(end_vertex=1))
+    assert res["dist"].tolist() == [0, 0, 6] and (res["end_v"] == 1).all() and (res["end_off"] == 2).all()
+    assert [list(p) for p in paths] == [[0, 1], [0, 1, 2, 1], [0, 1]]
+    # end vertex 0 cannot be reached from 1
+    res, _ = gw.align(ctx, graph, *reads_of([b"TT"]), np.array([1], np.int32), gw.opts(end_vertex=0))
+    assert res[0]["status"] == gw.ST_UNREACHABLE
+    with pytest.raises(gw.GwfaError) as e:
+        gw.align(ctx, graph, *reads_of([b"TT"]), np.array([1], np.int32), gw.opts(end_vertex=3))
+    assert e.value.code == gw.ERR_VERTEX
+    # per-query end vertex out of range: a per-query status
+    res, _ = gw.align(ctx, graph, *reads_of([b"TT", b"TT"]), np.array([1, 1], np.int32), None,
+                      v_end=np.array([1, 7], np.int32))
+    assert res[0]["status"] == 0 and res[0]["dist"] == 0 and res[1]["status"] == gw.ST_BAD_INPUT
+    graph.close()

@@ -333,3 +333,45 @@ def test_reverse_labels_equal_forward_suffix_runs():
                                   O._ptr(cost), len(ei), O._ptr(dst)) == 0
         for e in range(len(ei)):
             assert int(cost[e]) == O.dp_dense(g, q[int(ei[e]):], int(ev[e]))[0], (case, e)
+
+
+# ---------------------------------------------------------------------------
+# global form (Definition 2.2 with an end vertex)
+# ---------------------------------------------------------------------------
+def test_global_chains_equal_textbook_edit_distance():
+    """On a chain the global form is the pairwise edit distance between the
+    query and the labels from v_s through v_e."""
+    rng = np.random.default_rng(8201)
+    for case in range(80):
+        nv = int(rng.integers(1, 7))
+        labels = ["".join("ACGT"[x] for x in rng.integers(0, 4, size=int(rng.integers(1, 6)))) for _ in range(nv)]
+        edges = [(i, i + 1) for i in range(nv - 1)]
+        a = int(rng.integers(0, nv))
+        b = int(rng.integers(a, nv))
+        q = "".join("ACGT"[x] for x in rng.integers(0, 4, size=int(rng.integers(0, 14)))).encode()
+        want = refs.ed(q, "".join(labels[a:b + 1]).encode())
+        assert O.dp_dense_global((labels, edges), q, a, b) == want, case
+        assert O.gwf((labels, edges), q, a, v_e=b)["dist"] == want, case
+        if a > 0:   # v_e before v_s on the chain: unreachable
+            assert O.dp_dense_global((labels, edges), q, a, a - 1) == -1
+            assert O.gwf((labels, edges), q, a, v_e=a - 1)["status"] == 2
+
+
+def test_global_brute_force_random_tiny():
+    """Random tiny graphs with cycles and self-loops against walk
+    enumeration; the extension form's distance is never larger."""
+    rng = np.random.default_rng(8202)
+    n_reach = 0
+    for case in range(300):
+        labels, edges, q, v_s = refs.random_case(rng, n_vtx=int(rng.integers(1, 5)), max_label=3,
+                                                 p_edge=0.35, qlen=int(rng.integers(0, 6)))
+        v_e = int(rng.integers(0, len(labels)))
+        want = refs.brute_force_global(labels, edges, q, v_s, v_e)
+        got = O.dp_dense_global((labels, edges), q, v_s, v_e)
+        assert got == want, (case, labels, edges, q, v_s, v_e)
+        gw = O.gwf((labels, edges), q, v_s, v_e=v_e)
+        assert (gw["dist"] if gw["status"] == 0 else -1) == want, case
+        if want >= 0:
+            n_reach += 1
+            assert O.dp_dense((labels, edges), q, v_s)[0] <= want
+    assert n_reach > 150
