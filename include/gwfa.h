@@ -215,6 +215,27 @@ int gwfa_align_dump_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, con
                         int64_t *d_path_used, float *d_dump, int64_t dump_cap, int64_t *d_dump_count,
                         void *hip_stream);
 
+/* Base-level alignment of each query against the walk it was aligned to: the
+ * step that turns the walk of Algorithm 6 into an alignment (the paper leaves
+ * it to a pairwise aligner, noting that it is cheap).  Inputs are the device
+ * results and walks of a finished alignment call on the same queries
+ * (d_packed, d_read_off as given to it; d_res, d_path_buf as it filled them).
+ * For query r whose walk was traced, an optimal global alignment of q and the
+ * walk's string (labels of the walk, the last one cut at end_off) is written
+ * as CIGAR operations (length << 4 | op, op 7 '=', 8 'X', 1 'I' = query base
+ * absent from the walk, 2 'D' = walk base absent from the query) into
+ * d_cigar (cigar_cap words) at d_cigar_off[r], d_cigar_len[r] operations.
+ * Its cost (X + I + D) is the walk's edit distance: the distance for exact
+ * alignments, at most the distance under pruning.  d_cigar_len[r] = -1: no
+ * walk (status not OK or traceback off); -2: d_cigar too small
+ * (*d_cigar_used, device int64, receives the words needed); -3: internal
+ * capacity.  Synchronises the stream once to size its working memory, then
+ * runs asynchronously. */
+int gwfa_cigar_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, const uint64_t *d_packed,
+                   const int64_t *d_read_off, const gwfa_result *d_res, const int32_t *d_path_buf,
+                   uint32_t *d_cigar, int64_t cigar_cap, int64_t *d_cigar_off, int32_t *d_cigar_len,
+                   int64_t *d_cigar_used, void *hip_stream);
+
 /* ---- captured launches ---------------------------------------------------
  * A plan records the alignment of one device-resident batch (the arguments
  * of gwfa_align_batch_dev, fixed at creation) as a HIP graph: the reset of

@@ -75,6 +75,9 @@ struct gwfa_ctx {
     bool mlp_loaded = false;
     float* d_mlp_scr = nullptr;        // training activations, MLP_SCR_SAMPLES samples
     int64_t epoch = 0;                 // bumped when working memory is freed (invalidates plans)
+    char* d_cig_arena = nullptr;       // base-level alignment: per-workgroup regions
+    size_t cig_bytes = 0;
+    int32_t* d_cig_queue = nullptr;
     int n_cu = 256;
     std::string err;
 };
@@ -223,6 +226,8 @@ void gwfa_ctx_destroy(gwfa_ctx* c) {
     if (c->d_mlp) (void)hipFree(c->d_mlp);
     if (c->d_mlp_scale) (void)hipFree(c->d_mlp_scale);
     if (c->d_mlp_scr) (void)hipFree(c->d_mlp_scr);
+    if (c->d_cig_arena) (void)hipFree(c->d_cig_arena);
+    if (c->d_cig_queue) (void)hipFree(c->d_cig_queue);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -638,6 +643,72 @@ int gwfa_mlp_load(gwfa_ctx* ctx, const uint16_t* w, int64_t n, const float* scal
     HIPCHK(ctx, hipMemcpy(ctx->d_mlp, w, (size_t)n * 2, hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemcpy(ctx->d_mlp_scale, scale, 8 * 4, hipMemcpyHostToDevice));
     ctx->mlp_loaded = true;
+    return GWFA_OK;
+}
+
+int gwfa_cigar_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
+                   const int64_t* d_read_off, const gwfa_result* d_res, const int32_t* d_path_buf, uint32_t* d_cigar,
+                   int64_t cigar_cap, int64_t* d_cigar_off, int32_t* d_cigar_len, int64_t* d_cigar_used,
+                   void* hip_stream) {
+    if (!ctx || !g || n_reads < 0 || cigar_cap < 0 || g->device != ctx->device) return GWFA_ERR_ARG;
+    if (n_reads == 0) return GWFA_OK;
+    if (!d_packed || !d_read_off || !d_res || !d_path_buf || !d_cigar_off || !d_cigar_len || !d_cigar_used ||
+        (cigar_cap > 0 && !d_cigar))
+        return GWFA_ERR_ARG;
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    // sizes of the per-workgroup regions from the results (one synchronisation)
+    std::vector<gwfa_result> res((size_t)n_reads);
+    std::vector<int64_t> off((size_t)n_reads + 1);
+    HIPCHK(ctx, hipMemcpyAsync(res.data(), d_res, res.size() * sizeof(gwfa_result), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipMemcpyAsync(off.data(), d_read_off, off.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    int64_t max_d = 0, max_q = 0, max_path = 1, n_ok = 0;
+    for (int32_t r = 0; r < n_reads; ++r) {
+        const gwfa_result& x = res[r];
+        if (x.status != GWFA_ST_OK || x.path_off < 0 || x.path_len <= 0) continue;
+        ++n_ok;
+        max_d = std::max<int64_t>(max_d, x.dist);
+        max_q = std::max<int64_t>(max_q, off[r + 1] - off[r]);
+        max_path = std::max<int64_t>(max_path, x.path_len);
+    }
+    // the walk's string is at most |q| + d long (its edit distance to q is <= d)
+    const int64_t max_t = max_q + max_d;
+    if (max_t >= ((int64_t)1 << 31) || max_d > 46000) return GWFA_ERR_UNSUPPORTED;
+    CigArgs A;
+    memset(&A, 0, sizeof(A));
+    A.o_pref = align_up((max_t / 32 + 3) * 8, 256);
+    A.o_wf = A.o_pref + align_up((max_path + 2) * 8, 256);
+    A.o_ops = A.o_wf + align_up((max_d + 1) * (max_d + 1) * 4, 256);
+    A.arena_stride = A.o_ops + align_up((2 * max_d + 4) * 4, 4096);
+    // as many workgroups as fit in a 16 GiB region, at most two per compute unit
+    int64_t groups = std::min<int64_t>(std::max<int64_t>(n_ok, 1), (int64_t)ctx->n_cu * 2);
+    groups = std::max<int64_t>(1, std::min<int64_t>(groups, ((int64_t)16 << 30) / A.arena_stride));
+    const size_t need = (size_t)(A.arena_stride * groups);
+    if (need > ctx->cig_bytes) {
+        if (ctx->d_cig_arena) (void)hipFree(ctx->d_cig_arena);
+        ctx->d_cig_arena = nullptr;
+        ctx->cig_bytes = 0;
+        if (hipMalloc((void**)&ctx->d_cig_arena, need) != hipSuccess) {
+            ctx->d_cig_arena = nullptr;
+            return GWFA_ERR_NOMEM;
+        }
+        ctx->cig_bytes = need;
+    }
+    if (!ctx->d_cig_queue && hipMalloc((void**)&ctx->d_cig_queue, 4) != hipSuccess) {
+        ctx->d_cig_queue = nullptr;
+        return GWFA_ERR_NOMEM;
+    }
+    A.seg = g->d_seg; A.seg_off = g->d_seg_off;
+    A.rd = (const unsigned long long*)d_packed; A.rd_off = d_read_off; A.n_reads = n_reads;
+    A.res = d_res; A.path_buf = d_path_buf;
+    A.cigar = d_cigar; A.cigar_cap = d_cigar ? cigar_cap : 0;
+    A.cigar_cursor = (unsigned long long*)d_cigar_used;
+    A.cigar_off = d_cigar_off; A.cigar_len = d_cigar_len;
+    A.queue = ctx->d_cig_queue;
+    A.arena = ctx->d_cig_arena;
+    A.max_d = (int32_t)max_d; A.max_q = (int32_t)max_q; A.max_t = (int32_t)max_t;
+    HIPCHK(ctx, gwfa_launch_cigar(A, (int)groups, st));
     return GWFA_OK;
 }
 

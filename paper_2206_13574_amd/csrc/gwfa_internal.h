@@ -67,3 +67,24 @@ hipError_t gwfa_launch_mlp_adam(float* master, float* m1, float* m2, const float
 hipError_t gwfa_launch_mlp_cast(const float* src, uint16_t* dst, int64_t n, hipStream_t st);
 hipError_t gwfa_launch_mlp_logits(const float* feat, int64_t stride, const Scale8& scale, int64_t n,
                                   const uint16_t* w, float* out, hipStream_t st);
+
+// base-level alignment along the traced walks (gwfa_cigar.hip)
+struct CigArgs {
+    const unsigned long long* seg;   // packed labels
+    const int64_t* seg_off;
+    const unsigned long long* rd;    // packed queries
+    const int64_t* rd_off;
+    int32_t n_reads;
+    const gwfa_result* res;
+    const int32_t* path_buf;
+    uint32_t* cigar;
+    int64_t cigar_cap;
+    unsigned long long* cigar_cursor;
+    int64_t* cigar_off;
+    int32_t* cigar_len;
+    int32_t* queue;
+    char* arena;                     // one region per workgroup
+    int64_t arena_stride, o_pref, o_wf, o_ops;
+    int32_t max_d, max_q, max_t;     // capacities of the regions
+};
+hipError_t gwfa_launch_cigar(const CigArgs& A, int groups, hipStream_t st);

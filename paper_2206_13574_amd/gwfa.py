@@ -74,6 +74,7 @@ _SIGS = {
     "gwfa_label_entries": (ctypes.c_int, [_i32, _P, _P, _i64, _P, _P, _i32, _P, _P, _P, _i64, _P, _P, _P, _P,
                                           _P, _P, _P, _P, _i32]),
     "gwfa_stats": (ctypes.c_int, [_P, _P, _i32]),
+    "gwfa_cigar_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, _P, _i64, _P, _P, _P, _P]),
     "gwfa_plan_create": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64, _P,
                                         ctypes.POINTER(_P)]),
     "gwfa_plan_launch": (ctypes.c_int, [_P, _P]),
@@ -492,3 +493,29 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+CIGAR_OPS = {7: "=", 8: "X", 1: "I", 2: "D"}
+
+
+def cigar_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, cigar_cap: int = None):
+    """Base-level alignments of a finished alignment call (gwfa_cigar_dev):
+    returns (ops uint32 numpy, off int64 [n], len int32 [n])."""
+    torch = ctx.torch
+    n = batch.n
+    if cigar_cap is None:
+        cigar_cap = 4 * int(batch.bases) + 64 * n
+    cig = torch.zeros(max(cigar_cap, 1), dtype=torch.int32, device=ctx.tdev)
+    coff = torch.zeros(max(n, 1), dtype=torch.int64, device=ctx.tdev)
+    clen = torch.zeros(max(n, 1), dtype=torch.int32, device=ctx.tdev)
+    used = torch.zeros(1, dtype=torch.int64, device=ctx.tdev)
+    _check(_lib.gwfa_cigar_dev(ctx.h, graph.h, n, _tptr(batch.packed), _tptr(batch.read_off), _tptr(out.res),
+                               _tptr(out.path), _tptr(cig), int(cigar_cap), _tptr(coff), _tptr(clen), _tptr(used),
+                               _P(ctx.stream.cuda_stream)), "gwfa_cigar_dev", ctx.h)
+    torch.cuda.synchronize(ctx.tdev)
+    u = int(used.cpu().item())
+    return (cig[:min(u, cigar_cap)].cpu().numpy().view(np.uint32), coff[:n].cpu().numpy(), clen[:n].cpu().numpy())
+
+
+def cigar_string(ops: np.ndarray) -> str:
+    return "".join(f"{int(w) >> 4}{CIGAR_OPS[int(w) & 15]}" for w in ops)

@@ -194,3 +194,29 @@ def brute_force_global(labels, edges, q: bytes, v_s: int, v_e: int) -> int:
 
     dfs(v_s, list(range(n + 1)), 0)
     return best[0]
+
+
+CIGAR_OPS = {7: "=", 8: "X", 1: "I", 2: "D"}
+
+
+def cigar_cost(q: bytes, t: bytes, ops) -> int:
+    """Checks that CIGAR words (length << 4 | op) align q to t exactly (every
+    '=' pairs equal bases, every 'X' unequal ones, all of both strings
+    consumed) and returns the alignment's cost X + I + D."""
+    q, t = q.upper(), t.upper()
+    i = j = cost = 0
+    for w in ops:
+        n, op = int(w) >> 4, CIGAR_OPS[int(w) & 15]
+        assert n > 0
+        if op == "=":
+            assert q[i:i + n] == t[j:j + n]
+            i += n; j += n
+        elif op == "X":
+            assert all(q[i + x] != t[j + x] for x in range(n))
+            i += n; j += n; cost += n
+        elif op == "I":
+            i += n; cost += n
+        else:
+            j += n; cost += n
+    assert i == len(q) and j == len(t)
+    return cost
