@@ -44,6 +44,22 @@ def timed(ctx, graph, batch, out, o, repeats: int):
     return float(np.median(ms)), res
 
 
+def run_baselines(ctx, W, gate, period, run):
+    """The untrained network (same shape and scales, calibrated threshold) and
+    keep-all weights."""
+    rng = np.random.default_rng(4242)
+    w0 = train_prune.init_params(rng)
+    ctx.mlp_load(train_prune.to_bf16_bits(w0), W["scale"])
+    run("untrained network", gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=W["tau"], mlp_gate=gate,
+                                       mlp_period=period, traceback=False), "calibrated tau")
+    keep_all = np.zeros(gwfa.MLP_N, dtype=np.uint16)
+    keep_all[gwfa.MLP_N - 1] = 0x4120   # b3 = 10: every logit is 10
+    ctx.mlp_load(keep_all, W["scale"])
+    run("keep-all network", gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=0.0, mlp_gate=gate,
+                                      mlp_period=period, traceback=False))
+
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS))
@@ -56,6 +72,8 @@ def main(argv=None):
     ap.add_argument("--repeats", type=int, default=1)
     ap.add_argument("--lanes", type=int, default=256)
     ap.add_argument("--json", default=None, help="also write the rows to this file")
+    ap.add_argument("--no-baselines", action="store_true",
+                    help="skip the untrained and keep-all networks (each about as slow as exact or slower)")
     a = ap.parse_args(argv)
 
     import torch
@@ -99,17 +117,8 @@ def main(argv=None):
         run(f"learned tau={tau:+.3f}", gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=tau, mlp_gate=gate,
                                                  mlp_period=period, traceback=False),
             "calibrated" if abs(tau - W["tau"]) < 1e-6 else "")
-    # an untrained network of the same shape and scales, at the calibrated threshold
-    rng = np.random.default_rng(4242)
-    w0 = train_prune.init_params(rng)
-    ctx.mlp_load(train_prune.to_bf16_bits(w0), W["scale"])
-    run("untrained network", gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=W["tau"], mlp_gate=gate,
-                                       mlp_period=period, traceback=False), "calibrated tau")
-    keep_all = np.zeros(gwfa.MLP_N, dtype=np.uint16)
-    keep_all[gwfa.MLP_N - 1] = 0x4120   # b3 = 10: every logit is 10
-    ctx.mlp_load(keep_all, W["scale"])
-    run("keep-all network", gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=0.0, mlp_gate=gate,
-                                      mlp_period=period, traceback=False))
+    if not a.no_baselines:
+        run_baselines(ctx, W, gate, period, run)
 
     t_ex = rows[0]["ms"]
     w_ex = float(exact["work"].sum())
@@ -122,7 +131,7 @@ def main(argv=None):
             raise RuntimeError(f"{row['mode']}: a distance below the exact one")
         over = exc > 0
         row.update(bases_per_s=bases / (row["ms"] / 1000.0), speedup=t_ex / row["ms"],
-                   frac_over=float(over.mean()), mean_excess=float(exc.mean()),
+                   frac_over=float(over.mean()) if len(exc) else 0.0, mean_excess=float(exc.mean()) if len(exc) else 0.0,
                    mean_excess_over=float(exc[over].mean()) if over.any() else 0.0,
                    work_vs_exact=float(res["work"].sum()) / w_ex, not_ok=int((~ok).sum()), reads=r.n,
                    workload=a.workload, gate=gate, period=period)
