@@ -137,18 +137,28 @@ int ensure_tier(gwfa_ctx* ctx, int ti) {
     return GWFA_OK;
 }
 
+// Share of the device memory free at configuration time that each tier's
+// arenas may take (all three can be allocated at once).
+constexpr double TIER_SHARE[N_TIERS] = {0.45, 0.30, 0.10};
+
 void set_tiers(gwfa_ctx* ctx, int32_t dir_log2_max, int32_t list_cap) {
     // default: as many persistent workgroups as can be resident at once
     int per_cu = gwfa_align_blocks_per_cu(ctx->lanes);
     if (per_cu <= 0) per_cu = 4;
-    int groups = ctx->groups > 0 ? ctx->groups : ctx->n_cu * per_cu;
+    const int groups = ctx->groups > 0 ? ctx->groups : ctx->n_cu * per_cu;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b == 0) free_b = (size_t)64 << 30;
     for (int i = 0; i < N_TIERS; ++i) {
         free_tier(ctx->tier[i]);
         Tier& t = ctx->tier[i];
         t.dir_log2_max = std::min(dir_log2_max + 2 * i, 24);
         t.list_cap = (int32_t)std::min<int64_t>((int64_t)list_cap << (2 * i), (int64_t)1 << 26);
         t.cand_cap = (int32_t)std::min<int64_t>((int64_t)t.list_cap * 2, (int64_t)1 << 27);
-        t.groups = std::max(4, groups >> (3 * i));
+        layout(t);
+        // larger tiers keep as many workgroups as their share of memory holds:
+        // queries that overflow the first tier still run at full width
+        const int64_t fit = (int64_t)(TIER_SHARE[i] * (double)free_b) / t.stride;
+        t.groups = (int)std::max<int64_t>(4, std::min<int64_t>(groups, fit));
     }
 }
 
