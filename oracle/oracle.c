@@ -21,6 +21,9 @@
  *   orc_ed_banded   The same restricted to |i-j| <= D (exact when ED <= D).
  *   orc_dp_dense_global  The same rows; the answer is the cell
  *                   H_{|q|, v_e, |v_e|} (the global form with an end vertex).
+ *   orc_dp_dense_at Either form with the walk starting after the first j0
+ *                   bases of v_s: the initial condition moves to
+ *                   H_{0, v_s, j0} = 0 (a read seeded inside a vertex).
  *   orc_gwf         Algorithms 1-4 (Sections 2.4-2.5): the wavefront
  *                   driver, extension, expansion and the pruning heuristic,
  *                   in extension mode or, with an end vertex, the global
@@ -33,7 +36,9 @@
  * consumed entirely; the walk starts before the first base of v_s; the end
  * is free anywhere in the graph.  d* = min over the last query row.
  * End position: lexicographic minimum (v, j) over last-row cells equal to
- * d* with j >= 1, plus (v_s, 0) when that cell equals d*.
+ * d* with j >= 1, plus (v_s, 0) when that cell equals d*.  With a start
+ * offset j0 > 0 the start cell is (v_s, j0), already a j >= 1 cell, and
+ * (v_s, 0) is an ordinary j = 0 cell (not an end).
  *
  * Sequences are ASCII; bases compare case-insensitively.  Input validation
  * (alphabet, ranges) is the caller's job: the oracle assumes valid input.
@@ -138,7 +143,11 @@ static int row_fixpoint(const ograph *g, int32_t *h)
 
 /* Reads the answer off the last row: d* = row minimum; end = lexicographic
  * minimum (v,j) among cells equal to d* with j >= 1, or (v_s,0). */
-static void row_answer(const ograph *g, const int32_t *h, int32_t v_s, int32_t *out)
+/* End of the extension form: lexicographically smallest (v, j) holding the
+ * row minimum, over cells with j >= 1 plus the start cell (v_s, 0) when the
+ * walk starts at offset 0 (a cell (v, 0) otherwise ties with the end cell of
+ * a predecessor). */
+static void row_answer(const ograph *g, const int32_t *h, int32_t v_s, int32_t j0, int32_t *out)
 {
     int32_t best = INF_H;
     for (int64_t c = 0; c < g->ncell; c++) if (h[c] < best) best = h[c];
@@ -146,7 +155,7 @@ static void row_answer(const ograph *g, const int32_t *h, int32_t v_s, int32_t *
     for (int32_t v = 0; v < g->n; v++) {
         int64_t L = vlen(g, v);
         for (int64_t j = 0; j <= L; j++) {
-            if (j == 0 && v != v_s) continue;
+            if (j == 0 && !(v == v_s && j0 == 0)) continue;
             if (h[g->base[v] + j] == best) { out[1] = v; out[2] = (int32_t)j; return; }
         }
     }
@@ -155,7 +164,8 @@ static void row_answer(const ograph *g, const int32_t *h, int32_t v_s, int32_t *
 /* out[0]=d*, out[1]=end vertex, out[2]=end offset j, out[3]=max sweeps in a row.
  * Returns 0, or -1 on allocation failure / non-convergence. */
 /* Rows 0..|q| of Eq. 1; returns the last row (caller frees) or NULL. */
-static int32_t *dense_last_row(const ograph *g, const uint8_t *q, int32_t qlen, int32_t v_s, int *maxsw_out)
+static int32_t *dense_last_row(const ograph *g, const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0,
+                               int *maxsw_out)
 {
     int32_t n = g->n;
     const uint8_t *seq = g->seq;
@@ -164,9 +174,11 @@ static int32_t *dense_last_row(const ograph *g, const uint8_t *q, int32_t qlen, 
     int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * (size_t)g->ncell);
     if (!prev || !cur) { free(prev); free(cur); return NULL; }
     int maxsw = 0, rc = 0;
-    /* row 0: initial condition H_{0,v_s,0} = 0, everything else infinite */
+    /* row 0: initial condition H_{0,v_s,j0} = 0 (j0 = 0: the paper's
+     * H_{0,v_s,0}; j0 > 0 starts after the first j0 bases of v_s), everything
+     * else infinite */
     for (int64_t c = 0; c < g->ncell; c++) prev[c] = INF_H;
-    prev[g->base[v_s]] = 0;
+    prev[g->base[v_s] + j0] = 0;
     int sw = row_fixpoint(g, prev);
     if (sw < 0) rc = -1; else if (sw > maxsw) maxsw = sw;
     for (int32_t i = 1; i <= qlen && rc == 0; i++) {
@@ -201,9 +213,33 @@ int orc_dp_dense(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
     int maxsw = 0;
-    int32_t *last = dense_last_row(&g, q, qlen, v_s, &maxsw);
+    int32_t *last = dense_last_row(&g, q, qlen, v_s, 0, &maxsw);
     if (!last) { graph_free(&g); return -1; }
-    row_answer(&g, last, v_s, out);
+    row_answer(&g, last, v_s, 0, out);
+    out[3] = maxsw;
+    free(last); graph_free(&g);
+    return 0;
+}
+
+/* The same with the walk starting after the first j0 bases of v_s
+ * (0 <= j0 <= |v_s|) and, when v_e >= 0, the global form: out[0] is then
+ * H_{|q|, v_e, |v_e|} (-1 when unreachable), out[1] = v_e, out[2] = |v_e|. */
+int orc_dp_dense_at(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
+                    const int32_t *src, const int32_t *dst,
+                    const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t v_e, int32_t *out)
+{
+    ograph g;
+    if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
+    if (v_s < 0 || v_s >= n || v_e >= n || j0 < 0 || j0 > vlen(&g, v_s)) { graph_free(&g); return -1; }
+    int maxsw = 0;
+    int32_t *last = dense_last_row(&g, q, qlen, v_s, j0, &maxsw);
+    if (!last) { graph_free(&g); return -1; }
+    if (v_e < 0) {
+        row_answer(&g, last, v_s, j0, out);
+    } else {
+        int32_t h = last[g.base[v_e] + vlen(&g, v_e)];
+        out[0] = h >= INF_H ? -1 : h; out[1] = v_e; out[2] = (int32_t)vlen(&g, v_e);
+    }
     out[3] = maxsw;
     free(last); graph_free(&g);
     return 0;
@@ -219,7 +255,7 @@ int orc_dp_dense_global(int32_t n, const uint8_t *seq, const int64_t *off, int64
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
     int maxsw = 0;
-    int32_t *last = dense_last_row(&g, q, qlen, v_s, &maxsw);
+    int32_t *last = dense_last_row(&g, q, qlen, v_s, 0, &maxsw);
     if (!last) { graph_free(&g); return -1; }
     int32_t h = last[g.base[v_e] + vlen(&g, v_e)];
     out[0] = h >= INF_H ? -1 : h;
@@ -531,11 +567,12 @@ static int dq_push(dqueue *q, int32_t v, int32_t k)
  * s < counts_cap. */
 int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
             const int32_t *src, const int32_t *dst,
-            const uint8_t *q, int32_t qlen, int32_t v_s, int32_t v_e, int32_t a_diff, int32_t max_score,
-            int32_t *out, int64_t *work, int32_t *counts, int32_t counts_cap)
+            const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t v_e, int32_t a_diff,
+            int32_t max_score, int32_t *out, int64_t *work, int32_t *counts, int32_t counts_cap)
 {
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
+    if (v_s < 0 || v_s >= n || v_e >= n || j0 < 0 || j0 > vlen(&g, v_s)) { graph_free(&g); return -1; }
     hmap H = {0, 0, 0};
     dqueue Q = {0}, Qn = {0}, X = {0};
     int rc = 0;
@@ -543,11 +580,13 @@ int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
     work[0] = work[1] = work[2] = 0;
     if (hm_grow(&H)) { rc = -1; goto done; }
 
-    /* Algorithm 1: H~_{v_s,0} <- 0; Q <- [(v_s,0)]; d <- 0 */
+    /* Algorithm 1: H~_{v_s,0} <- 0; Q <- [(v_s,0)]; d <- 0.  A walk that
+     * starts after the first j0 bases of v_s starts on diagonal -j0 (the
+     * cell (0, v_s, j0)) at offset j0. */
     {
-        hent *e = hm_insert(&H, dkey(v_s, 0));
-        e->off = 0; e->W = 0; e->round = 0; e->pending = 0;
-        dq_push(&Q, v_s, 0);
+        hent *e = hm_insert(&H, dkey(v_s, -j0));
+        e->off = j0; e->W = 0; e->round = 0; e->pending = 0;
+        dq_push(&Q, v_s, -j0);
     }
     for (int32_t d = 0;; d++) {
         if (max_score >= 0 && d > max_score) { out[3] = 1; break; }
@@ -612,7 +651,7 @@ int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
                 hent *e = hm_find(&H, dkey(v, k));
                 if (k + e->off != qlen) continue;
                 found = 1;
-                if (e->off == 0 && v != v_s) continue;
+                if (e->off == 0 && !(v == v_s && j0 == 0)) continue;
                 if (bv < 0 || v < bv || (v == bv && e->off < bj)) { bv = v; bj = e->off; }
             }
             if (found) { out[0] = d; out[1] = bv; out[2] = bj; break; }

@@ -47,19 +47,19 @@ def semiglobal_ed_row(q: bytes, t: bytes) -> np.ndarray:
     return out
 
 
-def brute_force(labels, edges, q: bytes, v_s: int):
-    """Enumerates every walk from (v_s, 0) and every end position on its last
-    vertex, with an edit-distance column carried along the spelled string;
-    a branch is abandoned once its column minimum exceeds the best distance
-    found (the column minimum never decreases as the string grows).
-    Returns (d*, end set {(v, j)})."""
+def brute_force(labels, edges, q: bytes, v_s: int, j0: int = 0):
+    """Enumerates every walk from (v_s, j0) (after the first j0 bases of v_s)
+    and every end position on its last vertex, with an edit-distance column
+    carried along the spelled string; a branch is abandoned once its column
+    minimum exceeds the best distance found (the column minimum never
+    decreases as the string grows).  Returns (d*, end set {(v, j)})."""
     q = (q.decode() if isinstance(q, (bytes, bytearray)) else q).upper()
     n = len(q)
     succ = {}
     for a, b in edges:
         succ.setdefault(a, []).append(b)
     best = [n]                  # the empty prefix: all insertions
-    ends = {(v_s, 0)}           # dropped below as soon as something beats n
+    ends = {(v_s, j0)}          # dropped below as soon as something beats n
     qa = list(q)
 
     def step(col, c):
@@ -70,27 +70,28 @@ def brute_force(labels, edges, q: bytes, v_s: int):
 
     limit = 2 * n + 1
 
-    def dfs(v, col, depth):
+    def dfs(v, col, depth, first=0):
         lab = labels[v].upper()
-        for j, ch in enumerate(lab):
-            col = step(col, ch)
+        for j in range(first, len(lab)):
+            col = step(col, lab[j])
             depth += 1
             d = col[n]
             if d < best[0]:
                 best[0] = d
-                ends.clear()        # includes the empty-prefix (v_s, 0)
+                ends.clear()        # includes the empty-prefix start cell
             if d == best[0]:
                 ends.add((v, j + 1))
                 # the cell before v_s's first base also holds this value when
-                # the walk can step from here into v_s (zero-cost carry)
-                if j + 1 == len(lab) and v_s in succ.get(v, []):
+                # the walk can step from here into v_s (zero-cost carry); it
+                # is an end cell only when the walk starts there
+                if j + 1 == len(lab) and j0 == 0 and v_s in succ.get(v, []):
                     ends.add((v_s, 0))
             if min(col) > best[0] or depth > limit:
                 return
         for u in succ.get(v, []):
             dfs(u, col, depth)
 
-    dfs(v_s, list(range(n + 1)), 0)
+    dfs(v_s, list(range(n + 1)), 0, j0)
     return best[0], ends
 
 
@@ -145,10 +146,10 @@ def spell_random_walk(rng, labels, edges, v_s, max_len):
     return "".join(out).encode(), walk
 
 
-def brute_force_global(labels, edges, q: bytes, v_s: int, v_e: int) -> int:
-    """Global form with an end vertex: min over every walk from v_s to v_e of
-    the edit distance between q and the walk's whole spelled string; -1 when
-    v_e cannot be reached.  Walks longer than |q| + max(|q|, |S|) bases, S the
+def brute_force_global(labels, edges, q: bytes, v_s: int, v_e: int, j0: int = 0) -> int:
+    """Global form with an end vertex: min over every walk from v_s (after
+    its first j0 bases) to v_e of the edit distance between q and the walk's
+    whole spelled string; -1 when v_e cannot be reached.  Walks longer than |q| + max(|q|, |S|) bases, S the
     shortest walk, cannot be optimal (their cost exceeds S's), which bounds
     the enumeration on cyclic graphs."""
     import heapq
@@ -158,8 +159,8 @@ def brute_force_global(labels, edges, q: bytes, v_s: int, v_e: int) -> int:
     for a, b in edges:
         succ.setdefault(a, []).append(b)
     # shortest spelled length of a walk v_s ... v_e (whole labels)
-    dist = {v_s: len(labels[v_s])}
-    pq = [(len(labels[v_s]), v_s)]
+    dist = {v_s: len(labels[v_s]) - j0}
+    pq = [(len(labels[v_s]) - j0, v_s)]
     while pq:
         d, v = heapq.heappop(pq)
         if d > dist.get(v, 1 << 60):
@@ -181,8 +182,8 @@ def brute_force_global(labels, edges, q: bytes, v_s: int, v_e: int) -> int:
             new.append(min(col[i - 1] + (qa[i - 1] != c), col[i] + 1, new[i - 1] + 1))
         return new
 
-    def dfs(v, col, depth):
-        for ch in labels[v].upper():
+    def dfs(v, col, depth, first=0):
+        for ch in labels[v].upper()[first:]:
             col = step(col, ch)
             depth += 1
             if depth > limit or min(col) >= best[0]:
@@ -192,7 +193,7 @@ def brute_force_global(labels, edges, q: bytes, v_s: int, v_e: int) -> int:
         for u in succ.get(v, []):
             dfs(u, col, depth)
 
-    dfs(v_s, list(range(n + 1)), 0)
+    dfs(v_s, list(range(n + 1)), 0, j0)
     return best[0]
 
 

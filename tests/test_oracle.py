@@ -375,3 +375,83 @@ def test_global_brute_force_random_tiny():
             n_reach += 1
             assert O.dp_dense((labels, edges), q, v_s)[0] <= want
     assert n_reach > 150
+
+
+# ---------------------------------------------------------------------------
+# walks that start inside the start vertex (a read seeded at offset j0)
+# ---------------------------------------------------------------------------
+START_HAND = [
+    # graph, query, v_s, j0, d*, end(v, j)
+    # "GTCC" from offset 2 of ACG: G, then the T arm, then CC
+    ((["ACG", "T", "A", "CC"], [(0, 1), (0, 2), (1, 3), (2, 3)]), b"GTCC", 0, 2, 0, (3, 2)),
+    # the same query from offset 0 must delete "AC" first (or insert)
+    ((["ACG", "T", "A", "CC"], [(0, 1), (0, 2), (1, 3), (2, 3)]), b"GTCC", 0, 0, 2, (3, 2)),
+    # empty query from offset 1: distance 0 at the start cell (0, 1)
+    ((["ACG", "T"], [(0, 1)]), b"", 0, 1, 0, (0, 1)),
+    # starting at the end of v_s: the walk goes on into the successor
+    ((["ACG", "T"], [(0, 1)]), b"T", 0, 3, 0, (1, 1)),
+    # self-loop from offset 1: "C" then a full lap "AC"; the lap's end cell
+    # (0, 2) sorts before the zero-cost carry onto (0, 0), which is no end
+    # cell when the walk starts at offset 1
+    ((["AC"], [(0, 0)]), b"CAC", 0, 1, 0, (0, 2)),
+]
+
+
+@pytest.mark.parametrize("case", START_HAND)
+def test_start_offset_hand_cases(case):
+    g, q, vs, j0, d, end = case
+    assert O.dp_dense_at(g, q, vs, j0) == (d, end[0], end[1])
+    gw = O.gwf(g, q, vs, j0=j0)
+    assert (gw["dist"], gw["end_v"], gw["end_j"]) == (d, end[0], end[1])
+
+
+def test_start_offset_brute_force_random_tiny():
+    """Random tiny graphs (cycles, self-loops) with a random start offset:
+    the dense form and Algorithms 1-3 against walk enumeration from (v_s, j0),
+    in extension mode (d* and an end from the enumerated end set) and in the
+    global form."""
+    rng = np.random.default_rng(6113)
+    n_pos = 0
+    for case in range(300):
+        labels, edges, q, v_s = refs.random_case(rng, n_vtx=int(rng.integers(1, 5)), max_label=4,
+                                                 p_edge=0.35, qlen=int(rng.integers(0, 7)))
+        j0 = int(rng.integers(0, len(labels[v_s]) + 1))
+        n_pos += j0 > 0
+        g = (labels, edges)
+        bd, bends = refs.brute_force(labels, edges, q, v_s, j0)
+        d, ev, ej = O.dp_dense_at(g, q, v_s, j0)
+        assert d == bd and (ev, ej) == min(bends), (case, labels, edges, q, v_s, j0)
+        gw = O.gwf(g, q, v_s, j0=j0)
+        assert (gw["dist"], gw["end_v"], gw["end_j"]) == (d, ev, ej), case
+        v_e = int(rng.integers(0, len(labels)))
+        want = refs.brute_force_global(labels, edges, q, v_s, v_e, j0)
+        assert O.dp_dense_at(g, q, v_s, j0, v_e)[0] == want, (case, v_e)
+        gg = O.gwf(g, q, v_s, v_e=v_e, j0=j0)
+        assert (gg["dist"] if gg["status"] == 0 else -1) == want, case
+    assert n_pos > 150
+
+
+def test_start_offset_equals_cut_start_vertex():
+    """Starting after j0 bases of v_s equals starting at offset 0 of a new
+    vertex spelling the rest of v_s's label with v_s's out-edges (v_s itself
+    stays for walks that come back to it); ends map (new, j) -> (v_s, j0 + j)
+    and (new, 0) -> (v_s, j0)."""
+    rng = np.random.default_rng(77)
+    for case in range(200):
+        labels, edges, q, v_s = refs.random_case(rng, n_vtx=int(rng.integers(1, 6)), max_label=6,
+                                                 p_edge=0.3, qlen=int(rng.integers(0, 12)))
+        if len(labels[v_s]) < 2:
+            continue
+        j0 = int(rng.integers(1, len(labels[v_s])))
+        nv = len(labels)
+        nl = labels + [labels[v_s][j0:]]
+        ne = edges + [(nv, b) for a, b in edges if a == v_s]
+        d, ev, ej = O.dp_dense_at((labels, edges), q, v_s, j0)
+        d2, ev2, ej2, _ = O.dp_dense((nl, ne), q, nv)
+        assert d2 == d, case
+        # the new vertex sorts last; map its cells back before comparing
+        # with the cells the original graph reaches at d*
+        _, bends = refs.brute_force(labels, edges, q, v_s, j0)
+        assert (ev, ej) in bends
+        m = (v_s, j0 + ej2) if ev2 == nv else (ev2, ej2)
+        assert m in bends, case
