@@ -20,6 +20,10 @@
  * end vertex v_e; the distance is Eq. 1 at the cell (|q|, v_e, |v_e|) and
  * the end is (v_e, |v_e|).  One end vertex for every query
  * (opts.end_vertex >= 0) or one per query (gwfa_align_global_dev).
+ * Start offset (either form, gwfa_align_at_dev): the walk starts after the
+ * first j0 bases of the start vertex, i.e. Eq. 1's initial condition moves
+ * to the cell (0, v_s, j0) -- a read seeded inside a vertex.  The start cell
+ * is then (v_s, j0), and (v_s, 0) is no end cell when j0 > 0.
  *
  * Conventions for every call:
  *   - every int-returning call returns GWFA_OK (0) or a negative GWFA_ERR_*;
@@ -86,7 +90,7 @@ typedef struct {
     int32_t dist;           /* edit distance d*, -1 unless status == GWFA_ST_OK   */
     int32_t end_v;          /* end vertex                                          */
     int32_t end_off;        /* bases of end_v consumed, 1..|end_v| (0 only for the
-                               start vertex)                                       */
+                               start vertex with start offset 0)                   */
     int32_t status;         /* GWFA_ST_*                                           */
     int64_t path_off;       /* first vertex of the walk in path_buf, -1 if none    */
     int32_t path_len;       /* vertices in the walk (start ... end_v)              */
@@ -94,7 +98,10 @@ typedef struct {
     int64_t work;           /* sum over scores s of |F_s| (entries after extension) */
     int64_t t_begin;        /* device wall clock (100 MHz ticks) when the query   */
     int64_t t_end;          /* was taken from the work queue / finished           */
-} gwfa_result;              /* 56 bytes */
+    int32_t start_off;      /* bases of the walk's first vertex skipped (the start
+                               offset the query was given, 0 by default)           */
+    int32_t reserved;       /* 0                                                   */
+} gwfa_result;              /* 64 bytes */
 
 /* Default options: exact, traceback on, unbounded, extension mode. */
 void gwfa_opts_default(gwfa_opts *opts);
@@ -194,6 +201,19 @@ int gwfa_align_global_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, c
                           const int32_t *d_order, const gwfa_opts *opts, gwfa_result *d_res,
                           int32_t *d_path_buf, int64_t path_cap, int64_t *d_path_used, void *hip_stream);
 
+/* Both forms with per-query start offsets: d_start_off (device, n_reads
+ * int32, or NULL for all 0) gives j0, 0 <= j0 <= |v_start|, the bases of the
+ * start vertex before the walk's start; d_v_end (device, n_reads int32) the
+ * end vertices of the global form, or NULL for opts.end_vertex (then -1 is
+ * extension mode).  A query whose start offset or end vertex is out of range
+ * gets GWFA_ST_BAD_INPUT.  The walk written for a query begins with its
+ * start vertex; gwfa_result.start_off echoes j0.  Everything else as
+ * gwfa_align_batch_dev. */
+int gwfa_align_at_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, const uint64_t *d_packed,
+                      const int64_t *d_read_off, const int32_t *d_v_start, const int32_t *d_start_off,
+                      const int32_t *d_v_end, const int32_t *d_order, const gwfa_opts *opts, gwfa_result *d_res,
+                      int32_t *d_path_buf, int64_t path_cap, int64_t *d_path_used, void *hip_stream);
+
 /* The same, also writing one trace record per wavefront entry of every
  * score that is expanded (all scores before the final one), taken after the
  * extension and any pruning of that score, just before the expansion: the
@@ -221,7 +241,8 @@ int gwfa_align_dump_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, con
  * results and walks of a finished alignment call on the same queries
  * (d_packed, d_read_off as given to it; d_res, d_path_buf as it filled them).
  * For query r whose walk was traced, an optimal global alignment of q and the
- * walk's string (labels of the walk, the last one cut at end_off) is written
+ * walk's string (labels of the walk, the first one from start_off, the last
+ * one cut at end_off) is written
  * as CIGAR operations (length << 4 | op, op 7 '=', 8 'X', 1 'I' = query base
  * absent from the walk, 2 'D' = walk base absent from the query) into
  * d_cigar (cigar_cap words) at d_cigar_off[r], d_cigar_len[r] operations.

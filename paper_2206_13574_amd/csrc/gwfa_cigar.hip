@@ -3,7 +3,8 @@
 // aligner, noting that it is cheap).
 //
 // One persistent workgroup per query: the walk's string T (the labels of the
-// walk, the last one cut at end_off) is spelled into a 2-bit packed buffer,
+// walk, the first one from start_off, the last one cut at end_off) is
+// spelled into a 2-bit packed buffer,
 // then a pairwise wavefront alignment (the score-ordered diagonal recurrence
 // of Eq. 2 on a single path: mismatch, insertion, deletion, then extension
 // by the exact-match run) finds an optimal global alignment of q and T, and
@@ -88,12 +89,13 @@ __global__ __launch_bounds__(BLOCK) void k_cigar(CigArgs A) {
         const int64_t q0 = A.rd_off[r];
         const int32_t qlen = (int32_t)(A.rd_off[r + 1] - q0);
         if (res.status != GWFA_ST_OK || res.path_off < 0 || res.path_len <= 0 || res.dist > A.max_d ||
-            qlen > A.max_q) {
+            qlen > A.max_q || res.start_off < 0) {
             if (tid == 0) { A.cigar_off[r] = -1; A.cigar_len[r] = -1; }
             continue;
         }
         const int32_t* walk = A.path_buf + res.path_off;
         const int32_t L = res.path_len;
+        const int32_t j0 = res.start_off;
         // ---- prefix offsets of the walk's vertices in T (block scan in chunks)
         if (tid == 0) S.carry = 0;
         __syncthreads();
@@ -103,6 +105,7 @@ __global__ __launch_bounds__(BLOCK) void k_cigar(CigArgs A) {
             if (j < L) {
                 const int32_t v = walk[j];
                 len = (j == L - 1) ? (int64_t)res.end_off : (A.seg_off[v + 1] - A.seg_off[v]);
+                if (j == 0) len = max(len - j0, (int64_t)0);   // the first vertex starts at j0
             }
             // inclusive scan over the block (the lengths fit in 32 bits per vertex)
             int32_t x = (int32_t)len;
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(BLOCK) void k_cigar(CigArgs A) {
                 int32_t j = lo;
                 for (int b = 0; b < 32 && p < tlen; ++b, ++p) {
                     while (P[j + 1] <= p) ++j;
-                    const int64_t g = A.seg_off[walk[j]] + (p - P[j]);
+                    const int64_t g = A.seg_off[walk[j]] + (j == 0 ? j0 : 0) + (p - P[j]);
                     const ull c = (A.seg[g >> 5] >> (62 - 2 * (g & 31))) & 3ull;
                     word |= c << (62 - 2 * b);
                 }

@@ -16,6 +16,7 @@ struct KArgs {
     const unsigned long long* rd;    // packed queries
     const int64_t* rd_off;           // n_reads+1 base offsets
     const int32_t* v_start;
+    const int32_t* v_off;            // per-query start offsets in the start vertex, or null (all 0)
     const int32_t* order;            // work-queue order or null
     const int32_t* v_end;            // per-query end vertices (global form) or null
     int32_t end_vertex;              // end vertex of every query (global form) or -1

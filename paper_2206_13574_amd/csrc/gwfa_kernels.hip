@@ -258,6 +258,7 @@ struct Q {
     const ull* rd;
     int64_t q0;
     int32_t qlen, vs;
+    int32_t j0;       // start offset: the walk starts after the first j0 bases of vs
     int32_t ve;       // end vertex (global form) or -1 (extension mode)
     ull* dir;
     Page* pages;
@@ -291,10 +292,12 @@ __device__ __forceinline__ int record_entry(const Q& q, Shared& S, int32_t v, in
     // can advance it; in the global form the search goes on past i = |q|)
     if (mark || o == Lv || i == q.qlen) q.pages[d].R[k & 31] = mkR(q.gen, o);
     // end test: extension mode, any cell of the last query row; global form,
-    // the cell at the end of the end vertex (Algorithm 1)
+    // the cell at the end of the end vertex (Algorithm 1).  Offset-0 cells
+    // end a walk only at the start cell (vs, 0).
     if (i == q.qlen && (q.ve < 0 || (v == q.ve && o == Lv))) {
         S.found = 1;
-        if (q.ve >= 0 || o >= 1 || v == q.vs) atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
+        if (q.ve >= 0 || o >= 1 || (v == q.vs && q.j0 == 0))
+            atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
     }
     if (q.track) {
         atomicMax(&S.amax, i + W);
@@ -428,17 +431,20 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     q.qlen = (int32_t)(A.rd_off[r + 1] - q.q0);
     q.vs = A.v_start[r];
     q.ve = A.v_end ? A.v_end[r] : A.end_vertex;
+    q.j0 = A.v_off ? A.v_off[r] : 0;
     gwfa_result* out = A.res + r;
     const int64_t t_begin = (int64_t)wall_clock64();
-    if (q.vs < 0 || q.vs >= A.n_vtx || q.ve < -1 || q.ve >= A.n_vtx || (A.v_end && q.ve < 0)) {
+    const int64_t* __restrict__ seg_off = A.seg_off;
+    if (q.vs < 0 || q.vs >= A.n_vtx || q.ve < -1 || q.ve >= A.n_vtx || (A.v_end && q.ve < 0) || q.j0 < 0 ||
+        (int64_t)q.j0 > seg_off[q.vs + 1] - seg_off[q.vs]) {
         if (tid == 0) {
             out->t_begin = t_begin; out->t_end = t_begin;
             out->dist = -1; out->end_v = -1; out->end_off = -1; out->status = GWFA_ST_BAD_INPUT;
             out->path_off = -1; out->path_len = 0; out->n_scores = 0; out->work = 0;
+            out->start_off = q.j0; out->reserved = 0;
         }
         return;
     }
-    const int64_t* __restrict__ seg_off = A.seg_off;
     const int32_t* __restrict__ out_off = A.out_off;
     const int32_t* __restrict__ out_dst = A.out_dst;
     q.dir = reinterpret_cast<ull*>(arena + A.o_dir);
@@ -497,11 +503,11 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
         }
         __syncthreads();
         q.gen = __builtin_amdgcn_readfirstlane(S.gen);
-        if (tid == 0) {   // score 0 starts from the start diagonal (v_s, 0) at offset 0
-            const int ds = dir_insert(q.dir, mask, dkey(q.vs, 0), &S.dirn);
+        if (tid == 0) {   // score 0 starts from the start cell (0, vs, j0): diagonal -j0 at offset j0
+            const int ds = dir_insert(q.dir, mask, dkey(q.vs, (-q.j0) >> 5), &S.dirn);
             const int32_t t0 = q.tb ? trace_push(q, S, q.vs, -1) : -1;
             const Lists L0 = LL(0);
-            L0.v[0] = q.vs; L0.k[0] = 0; L0.o[0] = 0; L0.w[0] = 0; L0.t[0] = t0; L0.d[0] = ds;
+            L0.v[0] = q.vs; L0.k[0] = -q.j0; L0.o[0] = q.j0; L0.w[0] = 0; L0.t[0] = t0; L0.d[0] = ds;
             L0.b[0] = seg_off[q.vs];
             L0.l[0] = (int32_t)(seg_off[q.vs + 1] - seg_off[q.vs]);
             S.n_out = 1;
@@ -1080,6 +1086,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
         out->work = work;
         out->path_off = -1;
         out->path_len = 0;
+        out->start_off = q.j0;
+        out->reserved = 0;
         if (status == GWFA_ST_OK) {
             out->dist = s;
             out->end_v = (int32_t)(S.endkey >> 32);

@@ -34,8 +34,8 @@ PRUNE_NONE, PRUNE_HEURISTIC, PRUNE_LEARNED = 0, 1, 2
 
 RESULT_DTYPE = np.dtype([("dist", "<i4"), ("end_v", "<i4"), ("end_off", "<i4"), ("status", "<i4"),
                          ("path_off", "<i8"), ("path_len", "<i4"), ("n_scores", "<i4"), ("work", "<i8"),
-                         ("t_begin", "<i8"), ("t_end", "<i8")])
-assert RESULT_DTYPE.itemsize == 56
+                         ("t_begin", "<i8"), ("t_end", "<i8"), ("start_off", "<i4"), ("reserved", "<i4")])
+assert RESULT_DTYPE.itemsize == 64
 
 
 class Opts(ctypes.Structure):
@@ -63,6 +63,8 @@ _SIGS = {
                                             _P, _P]),
     "gwfa_align_global_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
                                              _P, _P]),
+    "gwfa_align_at_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
+                                         _P, _P]),
     "gwfa_align_dump_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
                                            _P, _P, _i64, _P, _P]),
     "gwfa_mlp_load": (ctypes.c_int, [_P, _P, _i64, _P]),
@@ -261,11 +263,19 @@ def pack_dev(ctx: Context, batch: DeviceBatch, err) -> None:
                               _P(ctx.stream.cuda_stream)), "gwfa_pack_dev", ctx.h)
 
 
-def align_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts, v_end=None) -> None:
+def align_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts, v_end=None,
+              start_off=None) -> None:
     """Aligns a device-resident batch (already packed) on ctx's stream.
     v_end: optional int32 device tensor of per-query end vertices (global
-    form, gwfa_align_global_dev)."""
+    form, gwfa_align_global_dev); start_off: optional int32 device tensor of
+    per-query start offsets in the start vertex (gwfa_align_at_dev)."""
     path_cap = int(out.path.numel()) if out.path is not None else 0
+    if start_off is not None:
+        _check(_lib.gwfa_align_at_dev(ctx.h, graph.h, batch.n, _tptr(batch.packed), _tptr(batch.read_off),
+                                      _tptr(batch.v_start), _tptr(start_off), _tptr(v_end), _tptr(batch.order),
+                                      ctypes.byref(o), _tptr(out.res), _tptr(out.path), path_cap,
+                                      _tptr(out.path_used), _P(ctx.stream.cuda_stream)), "gwfa_align_at_dev", ctx.h)
+        return
     if v_end is not None:
         _check(_lib.gwfa_align_global_dev(ctx.h, graph.h, batch.n, _tptr(batch.packed), _tptr(batch.read_off),
                                           _tptr(batch.v_start), _tptr(v_end), _tptr(batch.order), ctypes.byref(o),
@@ -278,10 +288,11 @@ def align_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o:
                                      _P(ctx.stream.cuda_stream)), "gwfa_align_batch_dev", ctx.h)
 
 
-def step_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts, v_end=None) -> None:
+def step_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts, v_end=None,
+             start_off=None) -> None:
     """One pass of the whole path on resident queries: pack, then align."""
     pack_dev(ctx, batch, out.err)
-    align_dev(ctx, graph, batch, out, o, v_end)
+    align_dev(ctx, graph, batch, out, o, v_end, start_off)
 
 
 def fetch(out: DeviceOut, n: int):
@@ -292,9 +303,11 @@ def fetch(out: DeviceOut, n: int):
     return res, path, used
 
 
-def align(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_cap: int = None, v_end=None):
+def align(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_cap: int = None, v_end=None,
+          start_off=None):
     """Convenience: host queries in, results out (through the device-side
-    entry points).  v_end: optional per-query end vertices (global form).
+    entry points).  v_end: optional per-query end vertices (global form);
+    start_off: optional per-query start offsets in the start vertex.
     Returns (results, paths) with paths a list of int32 arrays (or None when
     traceback is off)."""
     if o is None:
@@ -307,11 +320,11 @@ def align(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_ca
     if path_cap is None:
         path_cap = (int(off[-1]) + 64 * n) if o.traceback else 0
     out = alloc_out(ctx, n, path_cap)
-    ve = None
-    if v_end is not None:
-        ve = ctx.torch.from_numpy(np.ascontiguousarray(v_end, dtype=np.int32) if n else
-                                  np.zeros(1, np.int32)).to(ctx.tdev)
-    step_dev(ctx, graph, batch, out, o, ve)
+    def dev_i32(x):
+        return None if x is None else ctx.torch.from_numpy(
+            np.ascontiguousarray(x, dtype=np.int32) if n else np.zeros(1, np.int32)).to(ctx.tdev)
+
+    step_dev(ctx, graph, batch, out, o, dev_i32(v_end), dev_i32(start_off))
     ctx.torch.cuda.synchronize(ctx.tdev)
     if int(out.err.cpu().item()) != 0:
         raise GwfaError(ERR_ALPHABET, "gwfa_pack_dev")

@@ -37,7 +37,7 @@ def test_host_only_calls():
     assert gwfa.packed_words(0) == 2 and gwfa.packed_words(1) == 3 and gwfa.packed_words(64) == 4
     o = gwfa.opts()
     assert (o.prune, o.traceback, o.max_score, o.end_vertex, o.mlp_period) == (0, 1, -1, -1, 1)
-    assert gwfa.RESULT_DTYPE.itemsize == 56
+    assert gwfa.RESULT_DTYPE.itemsize == 64
     for code in range(-8, 1):
         assert gwfa._lib.gwfa_strerror(code)
     # argument checks that return before touching a device
