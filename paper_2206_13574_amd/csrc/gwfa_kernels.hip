@@ -53,6 +53,7 @@ constexpr int32_t CLAIM_BASE = 0x40000000;   // record value while a crossing ro
 constexpr int F_GROW = 1;   // directory / trace capacity exceeded: restart with a bigger one
 constexpr int F_LIST = 2;   // list / candidate capacity exceeded: re-run on a larger tier
 constexpr int XS_LDS = 1024;   // crossing entries sorted in LDS up to this many
+constexpr int NB_LDS = 512 + 4;   // staged batch of the expansion (largest block + halo)
 
 struct Page {
     ull R[PAGE];    // (gen << 32) | record offset (or CLAIM_BASE + round)
@@ -249,6 +250,9 @@ struct Shared {
     int32_t sidx[XS_LDS];
     int32_t xcnt[XS_LDS];   // merge: main-list entries below each crossing entry
     ull skeys2[64];         // crossing keys sorted by rank counting (small sets)
+    // expansion: the entries of one batch of the source list at slots 2 ..
+    // BLOCK+1 plus two neighbours on each side (slots 0, 1, BLOCK+2, BLOCK+3)
+    int32_t nbv[NB_LDS], nbk[NB_LDS], nbo[NB_LDS], nbd[NB_LDS], nbw[NB_LDS], nbt[NB_LDS];
     uint16_t mlpw[4808];    // pruning network (bfloat16), loaded once per launch
     float mscale[8];        // feature scales
 };
@@ -538,7 +542,6 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 int adm = 0;
                 for (int32_t base = 0; base < n; base += BLOCK) {
                     const int32_t idx = base + tid;
-                    const int lane = __lane_id();
                     const bool valid = idx < n;
                     // three fixed output slots: diagonals k-1, k, k+1
                     bool ov0 = false, ov1 = false, ov2 = false;
@@ -555,53 +558,39 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         if (q.track) W0 = Ls.w[p0];
                         if (q.tb) t0 = Ls.t[p0];
                     }
-                    // neighbours at merged positions idx-2 .. idx+2 are the entries of
-                    // the lanes around this one; lanes at the edge of the wave load
-                    // the ones that belong to another wave
-                    const int lm1 = lane >= 1 ? lane - 1 : lane, lm2 = lane >= 2 ? lane - 2 : lane;
-                    const int lp1 = lane <= 62 ? lane + 1 : lane, lp2 = lane <= 61 ? lane + 2 : lane;
-                    int32_t vm1 = __shfl(v, lm1, 64), km1 = __shfl(k, lm1, 64);
-                    int32_t vm2 = __shfl(v, lm2, 64), km2 = __shfl(k, lm2, 64);
-                    int32_t vp1 = __shfl(v, lp1, 64), kp1 = __shfl(k, lp1, 64), op1 = __shfl(o0, lp1, 64);
-                    int32_t dp1 = __shfl(ds0, lp1, 64);
-                    int32_t vp2 = __shfl(v, lp2, 64), kp2 = __shfl(k, lp2, 64), op2 = __shfl(o0, lp2, 64);
-                    int32_t wp1 = 0, wp2 = 0, tp1 = -1, tp2 = -1;
-                    if (q.track) { wp1 = __shfl(W0, lp1, 64); wp2 = __shfl(W0, lp2, 64); }
-                    if (q.tb) { tp1 = __shfl(t0, lp1, 64); tp2 = __shfl(t0, lp2, 64); }
-                    if (valid) {
-                        if (lane < 1) {
-                            vm1 = -1;
-                            if (idx >= 1) {
-                                const int32_t pp = vmx ? vm_phys(vmv, idx - 1, vm_below(vmv, idx - 1)) : idx - 1;
-                                vm1 = Ls.v[pp]; km1 = Ls.k[pp];
+                    // the neighbours at merged positions idx-2 .. idx+2 come from LDS:
+                    // every lane stages its entry, threads 0-3 load the two positions
+                    // on each side of the batch (in the same round as their own)
+                    {
+                        int32_t hv = -1, hk = 0, ho = 0, hd = 0, hw = 0, ht = -1;
+                        int hs = 0;
+                        if (tid < 4) {
+                            const int32_t hp = tid < 2 ? base - 2 + tid : base + BLOCK + (tid - 2);
+                            hs = tid < 2 ? tid : BLOCK + tid;
+                            if (hp >= 0 && hp < n) {
+                                const int32_t pp = vmx ? vm_phys(vmv, hp, vm_below(vmv, hp)) : hp;
+                                hv = Ls.v[pp]; hk = Ls.k[pp]; ho = Ls.o[pp]; hd = Ls.d[pp];
+                                if (q.track) hw = Ls.w[pp];
+                                if (q.tb) ht = Ls.t[pp];
                             }
                         }
-                        if (lane < 2) {
-                            vm2 = -1;
-                            if (idx >= 2) {
-                                const int32_t pp = vmx ? vm_phys(vmv, idx - 2, vm_below(vmv, idx - 2)) : idx - 2;
-                                vm2 = Ls.v[pp]; km2 = Ls.k[pp];
-                            }
-                        }
-                        if (lane > 62) {
-                            vp1 = -1;
-                            if (idx + 1 < n) {
-                                const int32_t pp = vmx ? vm_phys(vmv, idx + 1, vm_below(vmv, idx + 1)) : idx + 1;
-                                vp1 = Ls.v[pp]; kp1 = Ls.k[pp]; op1 = Ls.o[pp]; dp1 = Ls.d[pp];
-                                if (q.track) wp1 = Ls.w[pp];
-                                if (q.tb) tp1 = Ls.t[pp];
-                            }
-                        }
-                        if (lane > 61) {
-                            vp2 = -1;
-                            if (idx + 2 < n) {
-                                const int32_t pp = vmx ? vm_phys(vmv, idx + 2, vm_below(vmv, idx + 2)) : idx + 2;
-                                vp2 = Ls.v[pp]; kp2 = Ls.k[pp]; op2 = Ls.o[pp];
-                                if (q.track) wp2 = Ls.w[pp];
-                                if (q.tb) tp2 = Ls.t[pp];
-                            }
+                        S.nbv[tid + 2] = v; S.nbk[tid + 2] = k; S.nbo[tid + 2] = o0; S.nbd[tid + 2] = ds0;
+                        if (q.track) S.nbw[tid + 2] = W0;
+                        if (q.tb) S.nbt[tid + 2] = t0;
+                        if (tid < 4) {
+                            S.nbv[hs] = hv; S.nbk[hs] = hk; S.nbo[hs] = ho; S.nbd[hs] = hd;
+                            if (q.track) S.nbw[hs] = hw;
+                            if (q.tb) S.nbt[hs] = ht;
                         }
                     }
+                    lds_barrier();
+                    const int32_t vm1 = S.nbv[tid + 1], km1 = S.nbk[tid + 1];
+                    const int32_t vm2 = S.nbv[tid], km2 = S.nbk[tid];
+                    const int32_t vp1 = S.nbv[tid + 3], kp1 = S.nbk[tid + 3], op1 = S.nbo[tid + 3];
+                    const int32_t dp1 = S.nbd[tid + 3];
+                    const int32_t vp2 = S.nbv[tid + 4], kp2 = S.nbk[tid + 4], op2 = S.nbo[tid + 4];
+                    const int32_t wp1 = q.track ? S.nbw[tid + 3] : 0, wp2 = q.track ? S.nbw[tid + 4] : 0;
+                    const int32_t tp1 = q.tb ? S.nbt[tid + 3] : -1, tp2 = q.tb ? S.nbt[tid + 4] : -1;
                     // candidate outputs (before the record checks) and their first
                     // 32-base windows, fetched together with the records
                     int32_t c0 = -1, c1 = -1, c2 = -1;    // candidate offsets, -1 = none
@@ -665,9 +654,11 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             }
                         }
                     }
-                    // records of the diagonals outside F_s (k-1, k+1) and the windows
+                    // records of the diagonals outside F_s (k-1, k+1), the windows and
+                    // v's out-edge range (needed when an output reaches the vertex end)
                     const ull rw0 = (rec0 && pg0 >= 0) ? q.pages[pg0].R[(k - 1) & 31] : 0ull;
-                    // first out-edge of v, needed when an output reaches the vertex end
+                    const int32_t e0 = valid ? out_off[v] : 0;
+                    const int32_t e1 = valid ? out_off[v + 1] : 0;
 
                     const ull rw2 = (rec2 && pg2 >= 0) ? q.pages[pg2].R[(k + 1) & 31] : 0ull;
                     const int32_t m0 = (c0 >= 0) ? min(q.qlen - (k + c0 - 1), Lv - c0) : 0;
@@ -693,11 +684,14 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     }
                     // extension of the admitted outputs
                     int32_t lx0 = 0, lx1 = 0, lx2 = 0;
+                    int32_t dst0 = -1;
                     {
                         chunks += (ov0 && m0 > 0) + (ov1 && m1 > 0) + (ov2 && m2 > 0);
                         lx0 = ov0 ? (x0 ? min((int32_t)(__clzll((long long)x0) >> 1), m0) : min(32, m0)) : 0;
                         lx1 = ov1 ? (x1 ? min((int32_t)(__clzll((long long)x1) >> 1), m1) : min(32, m1)) : 0;
                         lx2 = ov2 ? (x2 ? min((int32_t)(__clzll((long long)x2) >> 1), m2) : min(32, m2)) : 0;
+                        // the first out-edge target, fetched before the long runs below
+                        dst0 = (e1 > e0) ? out_dst[e0] : -1;
                         // whole windows matched and bases remain: continue (one call
                         // site for the three outputs keeps the register demand down)
 #pragma unroll 1
@@ -737,8 +731,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             } else if (d < 0) {
                                 atomicOr(&S.flags, F_GROW);
                             } else {
-                                const int nc = record_entry(q, S, v, kj, o, Wj, d, nw, Lv,
-                                                            o == Lv ? out_off[v + 1] - out_off[v] : 0);
+                                const int nc = record_entry(q, S, v, kj, o, Wj, d, nw, Lv, o == Lv ? e1 - e0 : 0);
                                 if (nc) { endm |= 1 << j; deg = nc; }
                                 Ld.v[p] = v; Ld.k[p] = kj; Ld.o[p] = o; Ld.d[p] = d;
                                 Ld.l[p] = Lv; Ld.b[p] = sb;
@@ -753,7 +746,6 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         const int ncr = __popc(endm) * deg;
                         int cp = wave_alloc(ncr, &S.ncand);
                         if (endm) {
-                            const int32_t e0 = out_off[v];
 #pragma unroll
                             for (int j = 0; j < 3; ++j) {
                                 if (!((endm >> j) & 1)) continue;
@@ -764,7 +756,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                                 for (int e = 0; e < deg; ++e) {
                                     const int c = cp + e;
                                     if (c < A.cand_cap) {
-                                        cu[c] = out_dst[e0 + e]; ck[c] = k2; cW[c] = Wj; ct[c] = tj;
+                                        cu[c] = e == 0 ? dst0 : out_dst[e0 + e]; ck[c] = k2; cW[c] = Wj; ct[c] = tj;
                                     } else {
                                         atomicOr(&S.flags, F_LIST);
                                     }
@@ -789,23 +781,24 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 for (int32_t base = xlo; base < xhi; base += BLOCK) {
                     const int32_t idx = base + tid;
                     int ncr = 0;
-                    int32_t e0 = 0, k2 = 0, W = 0, t = 0;
+                    int32_t e0 = 0, k2 = 0, W = 0, t = 0, dst0 = -1;
                     if (idx < xhi) {
+                        // the entry carries its vertex's label (set when it was claimed),
+                        // so the extension's first loads go out with the out-edge range
                         const int32_t v = Ld.v[idx], k = Ld.k[idx], d = Ld.d[idx];
                         int32_t o = Ld.o[idx];
+                        const int64_t sb = Ld.b[idx];
+                        const int32_t Lv = Ld.l[idx];
                         W = (q.track || idx < preset_hi) ? Ld.w[idx] : 0;
                         t = (q.tb || idx < preset_hi) ? Ld.t[idx] : -1;
-                        if (idx >= preset_hi) {
-                            if (q.track) W = rval(q.pages[d].Wc[k & 31]);
-                            t = q.tb ? trace_push(q, S, v, t) : -1;
-                        }
-                        const int64_t sb = seg_off[v];
-                        const int32_t Lv = (int32_t)(seg_off[v + 1] - sb);
+                        if (idx >= preset_hi && q.track) W = rval(q.pages[d].Wc[k & 31]);
                         e0 = out_off[v];
                         const int32_t deg = out_off[v + 1] - e0;
                         ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, deg, chunks);
+                        if (ncr) dst0 = out_dst[e0];
+                        // Algorithm 5's push, after the extension so that their loads overlap
+                        if (idx >= preset_hi) t = q.tb ? trace_push(q, S, v, t) : -1;
                         Ld.o[idx] = o;
-                        Ld.l[idx] = Lv; Ld.b[idx] = sb;
                         if (q.track) Ld.w[idx] = W;
                         if (q.tb) Ld.t[idx] = t;
                         k2 = k + Lv;
@@ -815,7 +808,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         for (int e = 0; e < ncr; ++e) {
                             const int c = cp + e;
                             if (c < A.cand_cap) {
-                                cu[c] = out_dst[e0 + e]; ck[c] = k2; cW[c] = W; ct[c] = t;
+                                cu[c] = e == 0 ? dst0 : out_dst[e0 + e]; ck[c] = k2; cW[c] = W; ct[c] = t;
                             } else {
                                 atomicOr(&S.flags, F_LIST);
                             }
@@ -836,8 +829,14 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     const int32_t c = base + tid;
                     int claim = 0;
                     int ds = -1;
+                    int64_t csb = 0;
+                    int32_t cLv = 0;
                     if (c < nc) {
-                        ds = dir_insert(q.dir, mask, dkey(cu[c], ck[c] >> 5), &S.dirn);
+                        // the target's label, stored with the entry when it is claimed
+                        const int32_t u = cu[c];
+                        csb = seg_off[u];
+                        cLv = (int32_t)(seg_off[u + 1] - csb);
+                        ds = dir_insert(q.dir, mask, dkey(u, ck[c] >> 5), &S.dirn);
                         if (ds < 0) {
                             atomicOr(&S.flags, F_GROW);
                         } else {
@@ -858,6 +857,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     if (claim) {
                         if (pos < A.list_cap) {
                             Ld.v[pos] = cu[c]; Ld.k[pos] = ck[c]; Ld.o[pos] = 0; Ld.d[pos] = ds;
+                            Ld.l[pos] = cLv; Ld.b[pos] = csb;
                             if (q.track) Ld.w[pos] = cW[c];
                             if (q.tb) Ld.t[pos] = ct[c];
                         } else {
