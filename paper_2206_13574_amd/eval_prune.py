@@ -20,7 +20,7 @@ import time
 
 import numpy as np
 
-from . import gwfa, synth, train_prune
+from . import gwfa, synth, train_prune, tune
 
 WORKLOADS = {"cfg1": synth.cfg1, "cfg2": synth.cfg2, "cfg3": synth.cfg3, "cfg4": synth.cfg4}
 
@@ -70,7 +70,7 @@ def main(argv=None):
     ap.add_argument("--gate", type=int, default=None)
     ap.add_argument("--period", type=int, default=None)
     ap.add_argument("--repeats", type=int, default=1)
-    ap.add_argument("--lanes", type=int, default=256)
+    ap.add_argument("--lanes", type=int, default=None, help="lanes per query (default: the tuned configuration)")
     ap.add_argument("--json", default=None, help="also write the rows to this file")
     ap.add_argument("--no-baselines", action="store_true",
                     help="skip the untrained and keep-all networks (each about as slow as exact or slower)")
@@ -85,7 +85,11 @@ def main(argv=None):
     log(f"{a.workload}: {r.n} reads, {bases} bases, {g.n_vtx} V ({time.time() - t0:.1f} s)")
     stream = torch.cuda.Stream(device=torch.device("cuda", 0))
     ctx = gwfa.Context(0, stream=stream)
-    ctx.config(lanes=a.lanes)
+    cfg = tune.best_config(a.workload)
+    if a.lanes:
+        cfg["lanes"] = a.lanes
+    ctx.config(**cfg)
+    log(f"launch configuration {cfg}")
     graph = gwfa.Graph.of(ctx, g)
     with torch.cuda.stream(stream):
         batch = gwfa.upload_reads(ctx, r.seq, r.off, r.v_start)
