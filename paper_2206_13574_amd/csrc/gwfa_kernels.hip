@@ -1149,42 +1149,49 @@ __global__ __launch_bounds__(BLOCK, MODE == 2 ? 2 : (BLOCK >= 512 ? 1 : 3)) void
     }
 }
 
-// ASCII -> 2-bit packed words; one thread per output word (32 bases).
+// Four ASCII bases (the first in the low byte) -> 8 bits, the first base in
+// the high bits; A/a 0, C/c 1, G/g 2, T/t 3 come from bits 1-2 of the code
+// point ((c >> 1) ^ (c >> 2)).  *bad gets a bit for every other byte.
+__device__ __forceinline__ uint32_t pack4(uint32_t x, uint32_t& bad) {
+    const uint32_t u = x & 0xDFDFDFDFu;   // upper case
+    // 0x80 in every zero byte of v (exact: no carry crosses a byte)
+    auto zb = [](uint32_t v) { return ~(((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v | 0x7F7F7F7Fu); };
+    const uint32_t ok = zb(u ^ 0x41414141u) | zb(u ^ 0x43434343u) | zb(u ^ 0x47474747u) | zb(u ^ 0x54545454u);
+    bad |= ok ^ 0x80808080u;
+    const uint32_t m = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    return ((m & 0xFFu) << 6) | (((m >> 8) & 0xFFu) << 4) | (((m >> 16) & 0xFFu) << 2) | (m >> 24);
+}
+
+// ASCII -> 2-bit packed words.  One thread per 16 bases (one 16-byte load,
+// so a wave reads 1 KiB contiguously); lane pairs join their halves into one
+// 64-bit word (the even lane holds the first 16 bases).
 __global__ void k_pack(const uint8_t* __restrict__ ascii, int64_t n, ull* __restrict__ out, int64_t n_words,
                        int32_t* err) {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= n_words) return;
-    const int64_t b0 = w * 32;
-    ull word = 0;
-    int bad = 0;
-    if (b0 + 32 <= n && ((reinterpret_cast<uintptr_t>(ascii + b0) & 15) == 0)) {
-        const uint4* p = reinterpret_cast<const uint4*>(ascii + b0);
-        const uint4 x0 = p[0], x1 = p[1];
-        const uint32_t wd[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const uint32_t ch = (wd[j] >> (8 * c)) & 0xffu;
-                const uint32_t u = ch & 0xdfu;   // upper case
-                const uint32_t code = (u == 'A') ? 0u : (u == 'C') ? 1u : (u == 'G') ? 2u : (u == 'T') ? 3u : 4u;
-                bad |= code == 4u;
-                word = (word << 2) | (ull)(code & 3u);
+    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b0 = h * 16;
+    uint32_t half = 0, bad = 0;
+    if (h < 2 * n_words) {
+        if (b0 + 16 <= n && ((reinterpret_cast<uintptr_t>(ascii + b0) & 15) == 0)) {
+            const uint4 x = *reinterpret_cast<const uint4*>(ascii + b0);
+            half = (pack4(x.x, bad) << 24) | (pack4(x.y, bad) << 16) | (pack4(x.z, bad) << 8) | pack4(x.w, bad);
+        } else {
+            for (int j = 0; j < 16; ++j) {
+                const int64_t bi = b0 + j;
+                uint32_t code = 0;
+                if (bi < n) {
+                    const uint32_t c = ascii[bi];
+                    const uint32_t u = c & 0xdfu;
+                    bad |= (u != 'A' && u != 'C' && u != 'G' && u != 'T');
+                    code = ((c >> 1) ^ (c >> 2)) & 3u;
+                }
+                half = (half << 2) | code;
             }
-        }
-    } else {
-        for (int j = 0; j < 32; ++j) {
-            const int64_t bi = b0 + j;
-            uint32_t code = 0;
-            if (bi < n) {
-                const uint32_t u = ascii[bi] & 0xdfu;
-                code = (u == 'A') ? 0u : (u == 'C') ? 1u : (u == 'G') ? 2u : (u == 'T') ? 3u : 4u;
-                bad |= code == 4u;
-            }
-            word = (word << 2) | (ull)(code & 3u);
         }
     }
-    out[w] = word;
+    // every lane takes part in the exchange (blocks are whole waves, and lane
+    // pairs never straddle a wave)
+    const uint32_t other = __shfl_xor(half, 1, 64);
+    if (h < 2 * n_words && (h & 1) == 0) out[h >> 1] = ((ull)half << 32) | other;
     if (bad && err) atomicExch(err, (int32_t)GWFA_ERR_ALPHABET);
 }
 
@@ -1238,7 +1245,7 @@ hipError_t gwfa_launch_pack(const uint8_t* ascii, int64_t n, unsigned long long*
                             hipStream_t st) {
     if (n_words <= 0) return hipSuccess;
     const int tpb = 256;
-    const int64_t blocks = (n_words + tpb - 1) / tpb;
+    const int64_t blocks = (2 * n_words + tpb - 1) / tpb;   // one thread per 16 bases
     (void)hipGetLastError();
     hipLaunchKernelGGL(gwfa_dev::k_pack, dim3((unsigned)blocks), dim3(tpb), 0, st, ascii, n, out, n_words, err);
     return hipGetLastError();
