@@ -153,17 +153,20 @@ __device__ int dir_insert(ull* dir, uint32_t mask, ull key, int* n_ins) {
     return -1;
 }
 
-// Exclusive prefix sum of x over the 64 lanes of the wave, plus the total.
+// Exclusive prefix sum of x >= 0 over the 64 lanes of the wave, plus the
+// total.  Bit plane b adds 2^b times the number of lower lanes that have
+// bit b set (ballot + mbcnt): no data moves between lanes, one ballot per
+// bit plane in use (the counts here are small: outputs, claims, keeps).
 __device__ __forceinline__ int wave_excl_scan(int x, int& total) {
-    const int lane = __lane_id();
-    int incl = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += y;
+    uint32_t rem = (uint32_t)x;
+    int ex = 0, tot = 0;
+    for (int b = 0; __ballot(rem != 0u); ++b, rem >>= 1) {
+        const ull m = __ballot(rem & 1u);
+        ex += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
+        tot += __popcll(m) << b;
     }
-    total = __shfl(incl, 63, 64);
-    return incl - x;
+    total = tot;
+    return ex;
 }
 
 // Reserves cnt consecutive slots of an LDS counter (one atomic per wave,
