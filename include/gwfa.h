@@ -52,6 +52,7 @@ extern "C" {
 #define GWFA_ERR_DEVICE      -6   /* a HIP call failed (see gwfa_last_error)    */
 #define GWFA_ERR_PATH_CAP    -7   /* path buffer too small; distances valid     */
 #define GWFA_ERR_UNSUPPORTED -8   /* option not available (see each call)       */
+#define GWFA_ERR_FORMAT      -9   /* malformed GFA text (see gwfa_gfa_parse)     */
 
 /* ---- per-query status (gwfa_result.status) ----------------------------- */
 #define GWFA_ST_OK        0
@@ -256,6 +257,44 @@ int gwfa_cigar_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, const ui
                    const int64_t *d_read_off, const gwfa_result *d_res, const int32_t *d_path_buf,
                    uint32_t *d_cigar, int64_t cigar_cap, int64_t *d_cigar_off, int32_t *d_cigar_len,
                    int64_t *d_cigar_used, void *hip_stream);
+
+/* ---- GFA input ----------------------------------------------------------
+ * Reads a sequence graph from GFA 1 text, the format pangenome graphs are
+ * distributed in, into the arguments of gwfa_graph_create (Definition 2.1:
+ * vertices labelled by strings, directed edges).  Host memory only: these
+ * calls touch no device and need no context.
+ *   S <name> <sequence> ...     a segment; the sequence is over ACGT/acgt
+ *   L <a> <+|-> <b> <+|-> <overlap> ...   a link between oriented segments
+ * Other record types are ignored.  Segment i (in file order) becomes vertex
+ * 2i, its sequence, and vertex 2i+1, its reverse complement; a link
+ * (a, oa, b, ob) becomes the edge a^oa -> b^ob and its complement
+ * b^(-ob) -> a^(-oa), the same adjacency read on the other strand.  With
+ * flags = GWFA_GFA_FORWARD, segment i is vertex i and only links + + are
+ * kept (the others are counted in n_skipped).  Repeated edges are merged;
+ * edges are sorted by (source, target).  Errors (with *err_line, 1-based,
+ * when not NULL): GWFA_ERR_FORMAT for a malformed S or L record, a repeated
+ * segment name or no segment at all; GWFA_ERR_ALPHABET for a base outside
+ * ACGT; GWFA_ERR_EMPTY_LABEL for an empty sequence; GWFA_ERR_UNSUPPORTED for
+ * a sequence given as '*' or an overlap other than '*' or 0M; GWFA_ERR_VERTEX
+ * for a link naming an unknown segment; GWFA_ERR_ARG for an unreadable file
+ * or bad arguments. */
+#define GWFA_GFA_FORWARD 1
+typedef struct gwfa_gfa gwfa_gfa;
+int gwfa_gfa_load(const char *path, int32_t flags, gwfa_gfa **out, int64_t *err_line);
+int gwfa_gfa_parse(const char *text, int64_t len, int32_t flags, gwfa_gfa **out, int64_t *err_line);
+/* Sizes of the graph (any pointer may be NULL). */
+int gwfa_gfa_sizes(const gwfa_gfa *g, int32_t *n_vtx, int64_t *n_bases, int64_t *n_edge, int32_t *n_segments,
+                   int64_t *n_skipped);
+/* Copies the graph into caller buffers of the sizes above: seq (n_bases
+ * bytes), seq_off (n_vtx + 1), edge_src and edge_dst (n_edge each). */
+int gwfa_gfa_graph(const gwfa_gfa *g, uint8_t *seq, int64_t *seq_off, int32_t *edge_src, int32_t *edge_dst);
+/* Vertex of segment `name` in orientation reverse (0: as given, 1: reverse
+ * complement); GWFA_ERR_VERTEX if there is none. */
+int32_t gwfa_gfa_vertex(const gwfa_gfa *g, const char *name, int32_t reverse);
+/* Segment name of vertex v (storage owned by g) and its orientation in
+ * *reverse; NULL if v is out of range. */
+const char *gwfa_gfa_name(const gwfa_gfa *g, int32_t v, int32_t *reverse);
+void gwfa_gfa_free(gwfa_gfa *g);
 
 /* ---- captured launches ---------------------------------------------------
  * A plan records the alignment of one device-resident batch (the arguments

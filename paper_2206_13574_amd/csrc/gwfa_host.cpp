@@ -191,6 +191,7 @@ const char* gwfa_strerror(int code) {
     case GWFA_ERR_DEVICE: return "HIP runtime error";
     case GWFA_ERR_PATH_CAP: return "path buffer too small";
     case GWFA_ERR_UNSUPPORTED: return "unsupported option";
+    case GWFA_ERR_FORMAT: return "malformed GFA input";
     default: return "unknown error";
     }
 }

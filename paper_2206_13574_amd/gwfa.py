@@ -28,7 +28,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ---- error / status codes (include/gwfa.h) ---------------------------------
 OK = 0
 ERR_ARG, ERR_VERTEX, ERR_ALPHABET, ERR_EMPTY_LABEL = -1, -2, -3, -4
-ERR_NOMEM, ERR_DEVICE, ERR_PATH_CAP, ERR_UNSUPPORTED = -5, -6, -7, -8
+ERR_NOMEM, ERR_DEVICE, ERR_PATH_CAP, ERR_UNSUPPORTED, ERR_FORMAT = -5, -6, -7, -8, -9
+GFA_FORWARD = 1
 ST_OK, ST_MAX_SCORE, ST_ARENA, ST_BAD_INPUT, ST_UNREACHABLE = 0, 1, 2, 3, 4
 PRUNE_NONE, PRUNE_HEURISTIC, PRUNE_LEARNED = 0, 1, 2
 
@@ -82,6 +83,13 @@ _SIGS = {
     "gwfa_plan_launch": (ctypes.c_int, [_P, _P]),
     "gwfa_plan_finish": (ctypes.c_int, [_P, _P]),
     "gwfa_plan_destroy": (None, [_P]),
+    "gwfa_gfa_load": (ctypes.c_int, [ctypes.c_char_p, _i32, ctypes.POINTER(_P), _P]),
+    "gwfa_gfa_parse": (ctypes.c_int, [ctypes.c_char_p, _i64, _i32, ctypes.POINTER(_P), _P]),
+    "gwfa_gfa_sizes": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "gwfa_gfa_graph": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "gwfa_gfa_vertex": (_i32, [_P, ctypes.c_char_p, _i32]),
+    "gwfa_gfa_name": (ctypes.c_char_p, [_P, _i32, _P]),
+    "gwfa_gfa_free": (None, [_P]),
 }
 
 MLP_N = 4801                      # parameters of the pruning network
@@ -532,3 +540,62 @@ def cigar_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, ci
 
 def cigar_string(ops: np.ndarray) -> str:
     return "".join(f"{int(w) >> 4}{CIGAR_OPS[int(w) & 15]}" for w in ops)
+
+
+class GFA:
+    """A sequence graph read from GFA 1 text (gwfa_gfa_*; host memory, no
+    device).  Segment i is vertex 2i and its reverse complement 2i+1 (or
+    vertex i with forward_only).  `graph` holds the arguments of
+    gwfa_graph_create as a synth.Graph."""
+
+    def __init__(self, path: str = None, text=None, forward_only: bool = False):
+        from . import synth
+        h = _P()
+        line = ctypes.c_int64(0)
+        flags = GFA_FORWARD if forward_only else 0
+        if text is not None:
+            data = text.encode() if isinstance(text, str) else bytes(text)
+            rc = _lib.gwfa_gfa_parse(data, len(data), flags, ctypes.byref(h), ctypes.byref(line))
+        else:
+            rc = _lib.gwfa_gfa_load(os.fsencode(path), flags, ctypes.byref(h), ctypes.byref(line))
+        if rc != OK:
+            raise GwfaError(rc, "gwfa_gfa_parse" if text is not None else "gwfa_gfa_load",
+                            f"line {line.value}" if line.value else "")
+        self.h = h
+        nv, nb, ne, ns, nsk = (ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(),
+                               ctypes.c_int64())
+        _check(_lib.gwfa_gfa_sizes(h, ctypes.byref(nv), ctypes.byref(nb), ctypes.byref(ne), ctypes.byref(ns),
+                                   ctypes.byref(nsk)), "gwfa_gfa_sizes")
+        seq = np.zeros(max(nb.value, 1), np.uint8)
+        off = np.zeros(nv.value + 1, np.int64)
+        src = np.zeros(max(ne.value, 1), np.int32)
+        dst = np.zeros(max(ne.value, 1), np.int32)
+        _check(_lib.gwfa_gfa_graph(h, _np_ptr(seq), _np_ptr(off), _np_ptr(src), _np_ptr(dst)), "gwfa_gfa_graph")
+        self.n_segments = ns.value
+        self.n_skipped = nsk.value
+        self.graph = synth.Graph(seq[:nb.value], off, src[:ne.value].copy(), dst[:ne.value].copy(),
+                                 pos=np.arange(nv.value, dtype=np.int64), meta=dict(source="gfa"))
+
+    def vertex(self, name: str, reverse: bool = False) -> int:
+        v = _lib.gwfa_gfa_vertex(self.h, name.encode(), int(bool(reverse)))
+        if v < 0:
+            raise GwfaError(v, "gwfa_gfa_vertex", name)
+        return int(v)
+
+    def name(self, v: int):
+        rev = ctypes.c_int32(0)
+        p = _lib.gwfa_gfa_name(self.h, int(v), ctypes.byref(rev))
+        if p is None:
+            raise GwfaError(ERR_VERTEX, "gwfa_gfa_name", str(v))
+        return p.decode(), bool(rev.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.gwfa_gfa_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -221,3 +221,63 @@ def cigar_cost(q: bytes, t: bytes, ops) -> int:
             j += n; cost += n
     assert i == len(q) and j == len(t)
     return cost
+
+
+_RC = str.maketrans("ACGTacgt", "TGCAtgca")
+
+
+def revcomp(s: str) -> str:
+    return s.translate(_RC)[::-1]
+
+
+def gfa_reference(text: str, forward_only: bool = False):
+    """Plain reading of GFA 1 S and L records (independent of the library's
+    parser): returns (labels, sorted unique edges, skipped links).  Segment i
+    is vertex 2i and its reverse complement 2i+1 (vertex i with
+    forward_only); a link a oa b ob gives a^oa -> b^ob and b^-ob -> a^-oa."""
+    names, seqs = {}, []
+    lines = [l.rstrip("\r") for l in text.split("\n")]
+    for l in lines:
+        f = l.split("\t")
+        if f[0] == "S":
+            names[f[1]] = len(seqs)
+            seqs.append(f[2])
+    edges, skipped = set(), 0
+    for l in lines:
+        f = l.split("\t")
+        if f[0] != "L":
+            continue
+        a, oa, b, ob = names[f[1]], f[2] == "-", names[f[3]], f[4] == "-"
+        if forward_only:
+            if oa or ob:
+                skipped += 1
+            else:
+                edges.add((a, b))
+            continue
+        u, w = 2 * a + oa, 2 * b + ob
+        edges.add((u, w))
+        edges.add((w ^ 1, u ^ 1))
+    if forward_only:
+        labels = list(seqs)
+    else:
+        labels = [x for s in seqs for x in (s, revcomp(s))]
+    return labels, sorted(edges), skipped
+
+
+def random_gfa(rng, n_seg=8, max_len=6, n_links=12, extras=True):
+    """Random GFA 1 text: segments, links with random orientations (self
+    links and repeats included), other record types mixed in, lines in a
+    shuffled order (links may come before their segments)."""
+    segs = ["".join("ACGTacgt"[x] for x in rng.integers(0, 8, size=int(rng.integers(1, max_len + 1))))
+            for _ in range(n_seg)]
+    recs = [f"S\ts{i}\t{s}\tLN:i:{len(s)}" for i, s in enumerate(segs)]
+    for _ in range(n_links):
+        a, b = rng.integers(0, n_seg, size=2)
+        oa, ob = "+-"[int(rng.integers(0, 2))], "+-"[int(rng.integers(0, 2))]
+        ov = ["0M", "*"][int(rng.integers(0, 2))]
+        recs.append(f"L\ts{a}\t{oa}\ts{b}\t{ob}\t{ov}")
+    if extras:
+        recs += ["P\tp1\ts0+,s1-\t*", "# comment", "W\tsample\t1\tchr1\t0\t5\t>s0<s1"]
+    order = rng.permutation(len(recs))
+    body = "\n".join(recs[i] for i in order)
+    return "H\tVN:Z:1.0\n" + body + ("\n" if rng.random() < 0.5 else "")
