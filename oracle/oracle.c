@@ -23,7 +23,9 @@
  *                   H_{|q|, v_e, |v_e|} (the global form with an end vertex).
  *   orc_dp_dense_at Either form with the walk starting after the first j0
  *                   bases of v_s: the initial condition moves to
- *                   H_{0, v_s, j0} = 0 (a read seeded inside a vertex).
+ *                   H_{0, v_s, j0} = 0 (a read seeded inside a vertex); with
+ *                   a window j0..j1, H_{0, v_s, j} = 0 for all of it (the
+ *                   walk's leading gap in v_s is free).
  *   orc_gwf         Algorithms 1-4 (Sections 2.4-2.5): the wavefront
  *                   driver, extension, expansion and the pruning heuristic,
  *                   in extension mode or, with an end vertex, the global
@@ -165,7 +167,7 @@ static void row_answer(const ograph *g, const int32_t *h, int32_t v_s, int32_t j
  * Returns 0, or -1 on allocation failure / non-convergence. */
 /* Rows 0..|q| of Eq. 1; returns the last row (caller frees) or NULL. */
 static int32_t *dense_last_row(const ograph *g, const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0,
-                               int *maxsw_out)
+                               int32_t j1, int *maxsw_out)
 {
     int32_t n = g->n;
     const uint8_t *seq = g->seq;
@@ -174,11 +176,12 @@ static int32_t *dense_last_row(const ograph *g, const uint8_t *q, int32_t qlen, 
     int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * (size_t)g->ncell);
     if (!prev || !cur) { free(prev); free(cur); return NULL; }
     int maxsw = 0, rc = 0;
-    /* row 0: initial condition H_{0,v_s,j0} = 0 (j0 = 0: the paper's
-     * H_{0,v_s,0}; j0 > 0 starts after the first j0 bases of v_s), everything
+    /* row 0: initial condition H_{0,v_s,j} = 0 for j0 <= j <= j1 (j0 = j1 =
+     * 0: the paper's H_{0,v_s,0}; j0 > 0 starts after the first j0 bases of
+     * v_s; j1 > j0 leaves the walk's start free in that window), everything
      * else infinite */
     for (int64_t c = 0; c < g->ncell; c++) prev[c] = INF_H;
-    prev[g->base[v_s] + j0] = 0;
+    for (int32_t j = j0; j <= j1; j++) prev[g->base[v_s] + j] = 0;
     int sw = row_fixpoint(g, prev);
     if (sw < 0) rc = -1; else if (sw > maxsw) maxsw = sw;
     for (int32_t i = 1; i <= qlen && rc == 0; i++) {
@@ -213,7 +216,7 @@ int orc_dp_dense(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
     int maxsw = 0;
-    int32_t *last = dense_last_row(&g, q, qlen, v_s, 0, &maxsw);
+    int32_t *last = dense_last_row(&g, q, qlen, v_s, 0, 0, &maxsw);
     if (!last) { graph_free(&g); return -1; }
     row_answer(&g, last, v_s, 0, out);
     out[3] = maxsw;
@@ -221,18 +224,20 @@ int orc_dp_dense(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
     return 0;
 }
 
-/* The same with the walk starting after the first j0 bases of v_s
- * (0 <= j0 <= |v_s|) and, when v_e >= 0, the global form: out[0] is then
- * H_{|q|, v_e, |v_e|} (-1 when unreachable), out[1] = v_e, out[2] = |v_e|. */
+/* The same with the walk starting after the first j (j0 <= j <= j1 <=
+ * |v_s|, free within the window; j1 < 0 means j1 = j0) bases of v_s and,
+ * when v_e >= 0, the global form: out[0] is then H_{|q|, v_e, |v_e|} (-1
+ * when unreachable), out[1] = v_e, out[2] = |v_e|. */
 int orc_dp_dense_at(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
                     const int32_t *src, const int32_t *dst,
-                    const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t v_e, int32_t *out)
+                    const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t j1, int32_t v_e, int32_t *out)
 {
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
-    if (v_s < 0 || v_s >= n || v_e >= n || j0 < 0 || j0 > vlen(&g, v_s)) { graph_free(&g); return -1; }
+    if (j1 < 0) j1 = j0;
+    if (v_s < 0 || v_s >= n || v_e >= n || j0 < 0 || j1 < j0 || j1 > vlen(&g, v_s)) { graph_free(&g); return -1; }
     int maxsw = 0;
-    int32_t *last = dense_last_row(&g, q, qlen, v_s, j0, &maxsw);
+    int32_t *last = dense_last_row(&g, q, qlen, v_s, j0, j1, &maxsw);
     if (!last) { graph_free(&g); return -1; }
     if (v_e < 0) {
         row_answer(&g, last, v_s, j0, out);
@@ -255,7 +260,7 @@ int orc_dp_dense_global(int32_t n, const uint8_t *seq, const int64_t *off, int64
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
     int maxsw = 0;
-    int32_t *last = dense_last_row(&g, q, qlen, v_s, 0, &maxsw);
+    int32_t *last = dense_last_row(&g, q, qlen, v_s, 0, 0, &maxsw);
     if (!last) { graph_free(&g); return -1; }
     int32_t h = last[g.base[v_e] + vlen(&g, v_e)];
     out[0] = h >= INF_H ? -1 : h;
@@ -567,12 +572,13 @@ static int dq_push(dqueue *q, int32_t v, int32_t k)
  * s < counts_cap. */
 int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
             const int32_t *src, const int32_t *dst,
-            const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t v_e, int32_t a_diff,
+            const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t j1, int32_t v_e, int32_t a_diff,
             int32_t max_score, int32_t *out, int64_t *work, int32_t *counts, int32_t counts_cap)
 {
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
-    if (v_s < 0 || v_s >= n || v_e >= n || j0 < 0 || j0 > vlen(&g, v_s)) { graph_free(&g); return -1; }
+    if (j1 < 0) j1 = j0;
+    if (v_s < 0 || v_s >= n || v_e >= n || j0 < 0 || j1 < j0 || j1 > vlen(&g, v_s)) { graph_free(&g); return -1; }
     hmap H = {0, 0, 0};
     dqueue Q = {0}, Qn = {0}, X = {0};
     int rc = 0;
@@ -581,12 +587,14 @@ int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
     if (hm_grow(&H)) { rc = -1; goto done; }
 
     /* Algorithm 1: H~_{v_s,0} <- 0; Q <- [(v_s,0)]; d <- 0.  A walk that
-     * starts after the first j0 bases of v_s starts on diagonal -j0 (the
-     * cell (0, v_s, j0)) at offset j0. */
-    {
-        hent *e = hm_insert(&H, dkey(v_s, -j0));
-        e->off = j0; e->W = 0; e->round = 0; e->pending = 0;
-        dq_push(&Q, v_s, -j0);
+     * starts after the first j bases of v_s starts on diagonal -j (the cell
+     * (0, v_s, j)) at offset j; a start window j0..j1 puts all of them in
+     * the score-0 wavefront. */
+    for (int32_t j = j0; j <= j1; j++) {
+        hent *e = hm_insert(&H, dkey(v_s, -j));
+        if (!e) { rc = -1; goto done; }
+        e->off = j; e->W = 0; e->round = 0; e->pending = 0;
+        if (dq_push(&Q, v_s, -j)) { rc = -1; goto done; }
     }
     for (int32_t d = 0;; d++) {
         if (max_score >= 0 && d > max_score) { out[3] = 1; break; }

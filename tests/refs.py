@@ -47,19 +47,22 @@ def semiglobal_ed_row(q: bytes, t: bytes) -> np.ndarray:
     return out
 
 
-def brute_force(labels, edges, q: bytes, v_s: int, j0: int = 0):
-    """Enumerates every walk from (v_s, j0) (after the first j0 bases of v_s)
-    and every end position on its last vertex, with an edit-distance column
-    carried along the spelled string; a branch is abandoned once its column
-    minimum exceeds the best distance found (the column minimum never
-    decreases as the string grows).  Returns (d*, end set {(v, j)})."""
+def brute_force(labels, edges, q: bytes, v_s: int, j0: int = 0, j1: int = None):
+    """Enumerates every walk from (v_s, j) for every start j in j0..j1
+    (after the first j bases of v_s; j1 = None: j0 only) and every end
+    position on its last vertex, with an edit-distance column carried along
+    the spelled string; a branch is abandoned once its column minimum
+    exceeds the best distance found (the column minimum never decreases as
+    the string grows).  Returns (d*, end set {(v, j)})."""
+    if j1 is None:
+        j1 = j0
     q = (q.decode() if isinstance(q, (bytes, bytearray)) else q).upper()
     n = len(q)
     succ = {}
     for a, b in edges:
         succ.setdefault(a, []).append(b)
     best = [n]                  # the empty prefix: all insertions
-    ends = {(v_s, j0)}          # dropped below as soon as something beats n
+    ends = {(v_s, j) for j in range(j0, j1 + 1)}   # dropped below as soon as something beats n
     qa = list(q)
 
     def step(col, c):
@@ -91,7 +94,8 @@ def brute_force(labels, edges, q: bytes, v_s: int, j0: int = 0):
         for u in succ.get(v, []):
             dfs(u, col, depth)
 
-    dfs(v_s, list(range(n + 1)), 0, j0)
+    for j in range(j0, j1 + 1):
+        dfs(v_s, list(range(n + 1)), 0, j)
     return best[0], ends
 
 
@@ -146,7 +150,16 @@ def spell_random_walk(rng, labels, edges, v_s, max_len):
     return "".join(out).encode(), walk
 
 
-def brute_force_global(labels, edges, q: bytes, v_s: int, v_e: int, j0: int = 0) -> int:
+def brute_force_global(labels, edges, q: bytes, v_s: int, v_e: int, j0: int = 0, j1: int = None) -> int:
+    """The minimum of the single-start form over the starts j0..j1."""
+    if j1 is not None and j1 > j0:
+        vals = [brute_force_global(labels, edges, q, v_s, v_e, j) for j in range(j0, j1 + 1)]
+        vals = [x for x in vals if x >= 0]
+        return min(vals) if vals else -1
+    return _brute_force_global(labels, edges, q, v_s, v_e, j0)
+
+
+def _brute_force_global(labels, edges, q: bytes, v_s: int, v_e: int, j0: int = 0) -> int:
     """Global form with an end vertex: min over every walk from v_s (after
     its first j0 bases) to v_e of the edit distance between q and the walk's
     whole spelled string; -1 when v_e cannot be reached.  Walks longer than |q| + max(|q|, |S|) bases, S the

@@ -455,3 +455,60 @@ def test_start_offset_equals_cut_start_vertex():
         assert (ev, ej) in bends
         m = (v_s, j0 + ej2) if ev2 == nv else (ev2, ej2)
         assert m in bends, case
+
+
+# ---------------------------------------------------------------------------
+# a free leading gap in the start vertex: any start in j0..j1 at no cost
+# ---------------------------------------------------------------------------
+def test_start_window_hand_cases():
+    g = (["ACGTACGG", "TT"], [(0, 1)])
+    # "GGTT": the window 0..8 lets the walk start at offset 6 of vertex 0
+    assert O.dp_dense_at(g, b"GGTT", 0, 0, j1=8) == (0, 1, 2)
+    # from offset 0 only: the best prefix is "ACGT" (three substitutions), as
+    # the textbook semi-global row of the chain's string says
+    assert O.dp_dense_at(g, b"GGTT", 0, 0)[0] == 3 == int(refs.semiglobal_ed_row(b"GGTT", b"ACGTACGGTT").min())
+    # a window that ends before the seed: the minimum over its four starts
+    d = O.dp_dense_at(g, b"GGTT", 0, 0, j1=3)[0]
+    assert d == min(O.dp_dense_at(g, b"GGTT", 0, j)[0] for j in range(4))
+    gw = O.gwf(g, b"GGTT", 0, j0=0, j1=8)
+    assert (gw["dist"], gw["end_v"], gw["end_j"]) == (0, 1, 2)
+
+
+def test_start_window_brute_force_random_tiny():
+    """Windows j0..j1 on random tiny graphs: the dense form and Algorithms
+    1-3 against walk enumeration from every start of the window (extension
+    mode: d* and the end; global form: the distance)."""
+    rng = np.random.default_rng(771)
+    n_win = 0
+    for case in range(300):
+        labels, edges, q, v_s = refs.random_case(rng, n_vtx=int(rng.integers(1, 5)), max_label=5,
+                                                 p_edge=0.35, qlen=int(rng.integers(0, 7)))
+        L = len(labels[v_s])
+        j0 = int(rng.integers(0, L + 1))
+        j1 = int(rng.integers(j0, L + 1))
+        n_win += j1 > j0
+        g = (labels, edges)
+        bd, bends = refs.brute_force(labels, edges, q, v_s, j0, j1)
+        d, ev, ej = O.dp_dense_at(g, q, v_s, j0, j1=j1)
+        assert d == bd and (ev, ej) == min(bends), (case, labels, edges, q, v_s, j0, j1)
+        gw = O.gwf(g, q, v_s, j0=j0, j1=j1)
+        assert (gw["dist"], gw["end_v"], gw["end_j"]) == (d, ev, ej), case
+        v_e = int(rng.integers(0, len(labels)))
+        want = refs.brute_force_global(labels, edges, q, v_s, v_e, j0, j1)
+        assert O.dp_dense_at(g, q, v_s, j0, v_e, j1=j1)[0] == want, (case, v_e)
+        gg = O.gwf(g, q, v_s, v_e=v_e, j0=j0, j1=j1)
+        assert (gg["dist"] if gg["status"] == 0 else -1) == want, case
+    assert n_win > 100
+
+
+def test_start_window_is_the_minimum_over_its_starts():
+    rng = np.random.default_rng(772)
+    for case in range(100):
+        labels, edges, q, v_s = refs.random_case(rng, n_vtx=int(rng.integers(1, 6)), max_label=8,
+                                                 p_edge=0.3, qlen=int(rng.integers(0, 12)))
+        L = len(labels[v_s])
+        j0 = int(rng.integers(0, L + 1))
+        j1 = int(rng.integers(j0, L + 1))
+        g = (labels, edges)
+        d = O.dp_dense_at(g, q, v_s, j0, j1=j1)[0]
+        assert d == min(O.dp_dense_at(g, q, v_s, j)[0] for j in range(j0, j1 + 1)), case
