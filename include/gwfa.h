@@ -100,7 +100,8 @@ typedef struct {
     int64_t t_begin;        /* device wall clock (100 MHz ticks) when the query   */
     int64_t t_end;          /* was taken from the work queue / finished           */
     int32_t start_off;      /* bases of the walk's first vertex skipped (the start
-                               offset the query was given, 0 by default)           */
+                               offset, or where in its start window the traced
+                               walk starts; 0 by default)                           */
     int32_t reserved;       /* 0                                                   */
 } gwfa_result;              /* 64 bytes */
 
@@ -204,16 +205,22 @@ int gwfa_align_global_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, c
 
 /* Both forms with per-query start offsets: d_start_off (device, n_reads
  * int32, or NULL for all 0) gives j0, 0 <= j0 <= |v_start|, the bases of the
- * start vertex before the walk's start; d_v_end (device, n_reads int32) the
- * end vertices of the global form, or NULL for opts.end_vertex (then -1 is
- * extension mode).  A query whose start offset or end vertex is out of range
- * gets GWFA_ST_BAD_INPUT.  The walk written for a query begins with its
- * start vertex; gwfa_result.start_off echoes j0.  Everything else as
- * gwfa_align_batch_dev. */
+ * start vertex before the walk's start; d_start_hi (device, n_reads int32,
+ * or NULL for j1 = j0; needs d_start_off) gives j1, j0 <= j1 <= |v_start|:
+ * the walk may start after any j in j0..j1 bases at no cost (Eq. 1 with
+ * H(0, v_start, j) = 0 across the window: a free leading gap in the start
+ * vertex); d_v_end (device, n_reads int32) the end vertices of the global
+ * form, or NULL for opts.end_vertex (then -1 is extension mode).  A query
+ * whose start window or end vertex is out of range gets GWFA_ST_BAD_INPUT.
+ * The walk written for a query begins with its start vertex;
+ * gwfa_result.start_off is the offset the traced walk starts after (j0 when
+ * traceback is off).  The cell (v_start, 0) ends a walk only when j0 = 0.
+ * Everything else as gwfa_align_batch_dev. */
 int gwfa_align_at_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, const uint64_t *d_packed,
                       const int64_t *d_read_off, const int32_t *d_v_start, const int32_t *d_start_off,
-                      const int32_t *d_v_end, const int32_t *d_order, const gwfa_opts *opts, gwfa_result *d_res,
-                      int32_t *d_path_buf, int64_t path_cap, int64_t *d_path_used, void *hip_stream);
+                      const int32_t *d_start_hi, const int32_t *d_v_end, const int32_t *d_order,
+                      const gwfa_opts *opts, gwfa_result *d_res, int32_t *d_path_buf, int64_t path_cap,
+                      int64_t *d_path_used, void *hip_stream);
 
 /* The same, also writing one trace record per wavefront entry of every
  * score that is expanded (all scores before the final one), taken after the

@@ -445,7 +445,8 @@ static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
                      const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_v_end,
                      const int32_t* d_order, const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf,
                      int64_t path_cap, int64_t* d_path_used, float* d_dump, int64_t dump_cap,
-                     int64_t* d_dump_count, void* hip_stream, const int32_t* d_start_off = nullptr) {
+                     int64_t* d_dump_count, void* hip_stream, const int32_t* d_start_off = nullptr,
+                     const int32_t* d_start_hi = nullptr) {
     if (!ctx) return GWFA_ERR_ARG;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     KArgs A;
@@ -453,6 +454,7 @@ static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
                        path_cap, d_path_used, d_dump, dump_cap, d_dump_count, A);
     if (rc || n_reads == 0) return rc;
     A.v_off = d_start_off;
+    A.v_off_hi = d_start_hi;
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, A.path_cursor, ctx->d_retry_count, A.dump_count, st));
     return run_tiers(ctx, A, 0, d_order, n_reads, false, st);
@@ -477,10 +479,12 @@ int gwfa_align_global_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, c
 
 int gwfa_align_at_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
                       const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_start_off,
-                      const int32_t* d_v_end, const int32_t* d_order, const gwfa_opts* opts, gwfa_result* d_res,
-                      int32_t* d_path_buf, int64_t path_cap, int64_t* d_path_used, void* hip_stream) {
+                      const int32_t* d_start_hi, const int32_t* d_v_end, const int32_t* d_order,
+                      const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
+                      int64_t* d_path_used, void* hip_stream) {
+    if (n_reads > 0 && d_start_hi && !d_start_off) return GWFA_ERR_ARG;
     return align_dev(ctx, g, n_reads, d_packed, d_read_off, d_v_start, d_v_end, d_order, opts, d_res, d_path_buf,
-                     path_cap, d_path_used, nullptr, 0, nullptr, hip_stream, d_start_off);
+                     path_cap, d_path_used, nullptr, 0, nullptr, hip_stream, d_start_off, d_start_hi);
 }
 
 int gwfa_align_dump_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,

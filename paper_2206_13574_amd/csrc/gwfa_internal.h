@@ -17,6 +17,7 @@ struct KArgs {
     const int64_t* rd_off;           // n_reads+1 base offsets
     const int32_t* v_start;
     const int32_t* v_off;            // per-query start offsets in the start vertex, or null (all 0)
+    const int32_t* v_off_hi;         // per-query end of a free start window, or null (= v_off)
     const int32_t* order;            // work-queue order or null
     const int32_t* v_end;            // per-query end vertices (global form) or null
     int32_t end_vertex;              // end vertex of every query (global form) or -1

@@ -189,6 +189,13 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("" ::: "memory");
 }
 
+// A 64-bit value that is the same in every lane, as a scalar.
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Exclusive prefix sum over the whole block in thread order (keeps lists
 // sorted).  All threads must call it.
 template <int BLOCK>
@@ -265,7 +272,7 @@ struct Q {
     const ull* rd;
     int64_t q0;
     int32_t qlen, vs;
-    int32_t j0;       // start offset: the walk starts after the first j0 bases of vs
+    int32_t j0, j1;   // start window: the walk starts after the first j bases of vs, j0 <= j <= j1
     int32_t ve;       // end vertex (global form) or -1 (extension mode)
     ull* dir;
     Page* pages;
@@ -434,16 +441,21 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     const int tid = threadIdx.x;
     Q q;
     q.rd = A.rd;
-    q.q0 = A.rd_off[r];
-    q.qlen = (int32_t)(A.rd_off[r + 1] - q.q0);
-    q.vs = A.v_start[r];
-    q.ve = A.v_end ? A.v_end[r] : A.end_vertex;
-    q.j0 = A.v_off ? A.v_off[r] : 0;
+    // The query's parameters are the same in every lane: readfirstlane keeps
+    // them in scalar registers (and the test below a branch of the whole wave).
+    q.q0 = uniform64(A.rd_off[r]);
+    q.qlen = __builtin_amdgcn_readfirstlane((int32_t)(A.rd_off[r + 1] - q.q0));
+    q.vs = __builtin_amdgcn_readfirstlane(A.v_start[r]);
+    q.ve = __builtin_amdgcn_readfirstlane(A.v_end ? A.v_end[r] : A.end_vertex);
+    q.j0 = __builtin_amdgcn_readfirstlane(A.v_off ? A.v_off[r] : 0);
+    q.j1 = __builtin_amdgcn_readfirstlane(A.v_off_hi ? A.v_off_hi[r] : q.j0);
     gwfa_result* out = A.res + r;
     const int64_t t_begin = (int64_t)wall_clock64();
     const int64_t* __restrict__ seg_off = A.seg_off;
-    if (q.vs < 0 || q.vs >= A.n_vtx || q.ve < -1 || q.ve >= A.n_vtx || (A.v_end && q.ve < 0) || q.j0 < 0 ||
-        (int64_t)q.j0 > seg_off[q.vs + 1] - seg_off[q.vs]) {
+    bool bad = q.vs < 0 || q.vs >= A.n_vtx || q.ve < -1 || q.ve >= A.n_vtx || (A.v_end && q.ve < 0) || q.j0 < 0 ||
+               q.j1 < q.j0;
+    if (!bad) bad = (int64_t)q.j1 > uniform64(seg_off[q.vs + 1] - seg_off[q.vs]);
+    if (bad) {
         if (tid == 0) {
             out->t_begin = t_begin; out->t_end = t_begin;
             out->dist = -1; out->end_v = -1; out->end_off = -1; out->status = GWFA_ST_BAD_INPUT;
@@ -510,15 +522,31 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
         }
         __syncthreads();
         q.gen = __builtin_amdgcn_readfirstlane(S.gen);
-        if (tid == 0) {   // score 0 starts from the start cell (0, vs, j0): diagonal -j0 at offset j0
-            const int ds = dir_insert(q.dir, mask, dkey(q.vs, (-q.j0) >> 5), &S.dirn);
-            const int32_t t0 = q.tb ? trace_push(q, S, q.vs, -1) : -1;
+        // score 0 starts from the start cells (0, vs, j), j0 <= j <= j1: diagonal
+        // -j at offset j, sorted by k (t = 0 is j1).  A start's trace record is
+        // (vs, -1 - j), so the traced walk tells where it started.
+        {
+            const int32_t nst = q.j1 - q.j0 + 1;
             const Lists L0 = LL(0);
-            L0.v[0] = q.vs; L0.k[0] = -q.j0; L0.o[0] = q.j0; L0.w[0] = 0; L0.t[0] = t0; L0.d[0] = ds;
-            L0.b[0] = seg_off[q.vs];
-            L0.l[0] = (int32_t)(seg_off[q.vs + 1] - seg_off[q.vs]);
-            S.n_out = 1;
+            const int64_t sb0 = seg_off[q.vs];
+            const int32_t lv0 = (int32_t)(seg_off[q.vs + 1] - sb0);
+            for (int32_t t = tid; t < min(nst, (int32_t)A.list_cap); t += BLOCK) {
+                const int32_t j = q.j1 - t;
+                const int ds = dir_insert(q.dir, mask, dkey(q.vs, (-j) >> 5), &S.dirn);
+                if (ds < 0) atomicOr(&S.flags, F_GROW);
+                const int32_t t0 = q.tb ? trace_push(q, S, q.vs, -1 - j) : -1;
+                L0.v[t] = q.vs; L0.k[t] = -j; L0.o[t] = j; L0.w[t] = 0; L0.t[t] = t0; L0.d[t] = ds;
+                L0.b[t] = sb0; L0.l[t] = lv0;
+            }
+            if (tid == 0) {
+                S.n_out = min(nst, (int32_t)A.list_cap);
+                if (nst > A.list_cap) atomicOr(&S.flags, F_LIST);
+            }
         }
+        __syncthreads();
+        // a start window that does not fit restarts with more working memory
+        const int f0 = __builtin_amdgcn_readfirstlane(S.flags | ((S.dirn > half || S.mn > half) ? F_GROW : 0));
+        const int32_t n_start = __builtin_amdgcn_readfirstlane(S.n_out);
         __syncthreads();
         cur = 1;
         n_cur = 0;
@@ -526,9 +554,10 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
         s = 0;
         work = 0;
         status = -1;
-        int rflags = 0;
+        int rflags = f0;
         chunks = 0;
         for (;; ++s) {
+            if (f0) break;
             const int nb = 1 - cur;
             const Lists Ld = LL(nb);
             int32_t n1 = 0;           // diagonals produced by the expansion
@@ -776,8 +805,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             }
             if (tid == 0) { const ull t2 = wall_clock64(); S.tick[0] += t2 - tk; tk = t2; }
             // ========== crossings (Algorithm 2, same score, cost 0), in rounds ==========
-            int32_t xlo = n1, xhi = (s == 0) ? 1 : n1;
-            const int32_t preset_hi = (s == 0) ? 1 : 0;   // the start entry has its W and t
+            int32_t xlo = n1, xhi = (s == 0) ? n_start : n1;
+            const int32_t preset_hi = (s == 0) ? n_start : 0;   // the start entries have their W and t
             bool restart = false;
             for (int round = 0;; ++round) {
                 // (1) extend the diagonals created by the previous round
@@ -1098,8 +1127,10 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             if (q.tb && S.tend >= 0) {
                 // a chain visits each trace slot at most once: at most mask+1 steps
                 const int32_t lim = (int32_t)q.mask + 1;
-                int32_t len = 0;
-                for (int32_t t = S.tend; t >= 0 && len <= lim; t = q.Tt[t]) ++len;
+                int32_t len = 0, first = -1;
+                for (int32_t t = S.tend; t >= 0 && len <= lim; t = q.Tt[t]) { ++len; first = t; }
+                // the first record's predecessor field holds -1 - (start offset)
+                if (first >= 0 && q.Tt[first] < 0) out->start_off = -1 - q.Tt[first];
                 const ull pos = atomicAdd(A.path_cursor, (ull)len);
                 out->path_len = len;
                 if ((int64_t)pos + len <= A.path_cap && A.path_buf) {

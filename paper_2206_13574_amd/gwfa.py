@@ -64,8 +64,8 @@ _SIGS = {
                                             _P, _P]),
     "gwfa_align_global_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
                                              _P, _P]),
-    "gwfa_align_at_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
-                                         _P, _P]),
+    "gwfa_align_at_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P,
+                                         _i64, _P, _P]),
     "gwfa_align_dump_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
                                            _P, _P, _i64, _P, _P]),
     "gwfa_mlp_load": (ctypes.c_int, [_P, _P, _i64, _P]),
@@ -272,15 +272,17 @@ def pack_dev(ctx: Context, batch: DeviceBatch, err) -> None:
 
 
 def align_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts, v_end=None,
-              start_off=None) -> None:
+              start_off=None, start_hi=None) -> None:
     """Aligns a device-resident batch (already packed) on ctx's stream.
     v_end: optional int32 device tensor of per-query end vertices (global
     form, gwfa_align_global_dev); start_off: optional int32 device tensor of
-    per-query start offsets in the start vertex (gwfa_align_at_dev)."""
+    per-query start offsets in the start vertex and start_hi the ends of free
+    start windows (gwfa_align_at_dev)."""
     path_cap = int(out.path.numel()) if out.path is not None else 0
     if start_off is not None:
         _check(_lib.gwfa_align_at_dev(ctx.h, graph.h, batch.n, _tptr(batch.packed), _tptr(batch.read_off),
-                                      _tptr(batch.v_start), _tptr(start_off), _tptr(v_end), _tptr(batch.order),
+                                      _tptr(batch.v_start), _tptr(start_off), _tptr(start_hi), _tptr(v_end),
+                                      _tptr(batch.order),
                                       ctypes.byref(o), _tptr(out.res), _tptr(out.path), path_cap,
                                       _tptr(out.path_used), _P(ctx.stream.cuda_stream)), "gwfa_align_at_dev", ctx.h)
         return
@@ -297,10 +299,10 @@ def align_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o:
 
 
 def step_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts, v_end=None,
-             start_off=None) -> None:
+             start_off=None, start_hi=None) -> None:
     """One pass of the whole path on resident queries: pack, then align."""
     pack_dev(ctx, batch, out.err)
-    align_dev(ctx, graph, batch, out, o, v_end, start_off)
+    align_dev(ctx, graph, batch, out, o, v_end, start_off, start_hi)
 
 
 def fetch(out: DeviceOut, n: int):
@@ -312,10 +314,11 @@ def fetch(out: DeviceOut, n: int):
 
 
 def align(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_cap: int = None, v_end=None,
-          start_off=None):
+          start_off=None, start_hi=None):
     """Convenience: host queries in, results out (through the device-side
     entry points).  v_end: optional per-query end vertices (global form);
-    start_off: optional per-query start offsets in the start vertex.
+    start_off: optional per-query start offsets in the start vertex; start_hi:
+    optional ends of free start windows (needs start_off).
     Returns (results, paths) with paths a list of int32 arrays (or None when
     traceback is off)."""
     if o is None:
@@ -332,7 +335,7 @@ def align(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_ca
         return None if x is None else ctx.torch.from_numpy(
             np.ascontiguousarray(x, dtype=np.int32) if n else np.zeros(1, np.int32)).to(ctx.tdev)
 
-    step_dev(ctx, graph, batch, out, o, dev_i32(v_end), dev_i32(start_off))
+    step_dev(ctx, graph, batch, out, o, dev_i32(v_end), dev_i32(start_off), dev_i32(start_hi))
     ctx.torch.cuda.synchronize(ctx.tdev)
     if int(out.err.cpu().item()) != 0:
         raise GwfaError(ERR_ALPHABET, "gwfa_pack_dev")

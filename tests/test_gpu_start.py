@@ -151,3 +151,82 @@ def test_start_offset_out_of_range_is_a_per_query_status(G):
         assert (res[2]["status"], res[2]["dist"], res[2]["end_v"], res[2]["end_off"]) == (0, 0, 1, 2)
     finally:
         graph.close()
+
+
+def test_start_window_tiny_random_graphs(G):
+    """Free start windows j0..j1 (both forms): distance, end and work
+    bit-exact against the oracle; the traced walk starts inside the window,
+    and re-scored from there it costs the distance."""
+    gw, ctx = G
+    rng = np.random.default_rng(5504)
+    cases = []
+    for _ in range(2000):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(1, 7)),
+                                                max_label=40 if rng.random() < 0.2 else 6, p_edge=0.35,
+                                                qlen=int(rng.integers(0, 30)))
+        L = len(labels[vs])
+        j0 = int(rng.integers(0, L + 1))
+        cases.append((labels, edges, q, vs, j0, int(rng.integers(j0, L + 1)), int(rng.integers(0, len(labels)))))
+    g, base = union_graph([c[:4] for c in cases])
+    graph = gw.Graph.of(ctx, g)
+    try:
+        seq, off = reads_of([c[2] for c in cases])
+        vs_all = np.array([c[3] + b for c, b in zip(cases, base)], np.int32)
+        j0s = np.array([c[4] for c in cases], np.int32)
+        j1s = np.array([c[5] for c in cases], np.int32)
+        say("start windows, extension form")
+        res, paths = gw.align(ctx, graph, seq, off, vs_all, start_off=j0s, start_hi=j1s,
+                              path_cap=int(off[-1]) * 4 + 256 * len(cases))
+        say("start windows, global form")
+        resg, pathsg = gw.align(ctx, graph, seq, off, vs_all, start_off=j0s, start_hi=j1s,
+                                v_end=np.array([c[6] + b for c, b in zip(cases, base)], np.int32),
+                                path_cap=int(off[-1]) * 4 + 256 * len(cases))
+    finally:
+        graph.close()
+    for i, (labels, edges, q, vs, j0, j1, ve) in enumerate(cases):
+        d, ev, ej = O.dp_dense_at((labels, edges), q, vs, j0, j1=j1)
+        wf = O.gwf((labels, edges), q, vs, j0=j0, j1=j1)
+        r = res[i]
+        assert (r["status"], r["dist"], r["end_v"] - base[i], r["end_off"], r["work"]) == \
+            (0, d, ev, ej, wf["work"]), (i, labels, edges, q, vs, j0, j1)
+        so = int(r["start_off"])
+        p = paths[i]
+        assert j0 <= so <= j1 and p[0] == vs + base[i] and O.is_walk(g, p)
+        assert O.ed_global(q, _spell_from(g, p, so, ej)) == d
+        dg = O.dp_dense_at((labels, edges), q, vs, j0, ve, j1=j1)[0]
+        rg = resg[i]
+        if dg < 0:
+            assert rg["status"] == gw.ST_UNREACHABLE, i
+            continue
+        wg = O.gwf((labels, edges), q, vs, v_e=ve, j0=j0, j1=j1)
+        assert (rg["status"], rg["dist"], rg["end_v"] - base[i], rg["work"]) == (0, dg, ve, wg["work"]), i
+        sg = int(rg["start_off"])
+        assert j0 <= sg <= j1
+        assert O.ed_global(q, _spell_from(g, pathsg[i], sg, len(labels[ve]))) == dg
+
+
+def test_start_window_longer_than_the_list_reruns(G):
+    """A window wider than the first tier's list capacity restarts on larger
+    tiers and still gives the oracle's answer."""
+    gw, ctx = G
+    rng = np.random.default_rng(5505)
+    lab = "".join("ACGT"[x] for x in rng.integers(0, 4, size=3000))
+    labels, edges = [lab, "ACGTTGCA"], [(0, 1)]
+    g = synth.Graph.from_labels(labels, edges)
+    qs = [lab[2500:2600].encode() + b"ACGT", lab[10:60].encode(), lab[2990:].encode() + b"ACGTT"]
+    c2 = gw.Context(0)
+    c2.config(list_cap=1024)
+    graph = gw.Graph.of(c2, g)
+    try:
+        say("window of 3,001 starts, list capacity 1,024")
+        seq, off = reads_of(qs)
+        res, paths = gw.align(c2, graph, seq, off, np.zeros(3, np.int32), start_off=np.zeros(3, np.int32),
+                              start_hi=np.full(3, 3000, np.int32))
+        for i, q in enumerate(qs):
+            assert (res[i]["status"], res[i]["dist"], res[i]["end_v"], res[i]["end_off"]) == \
+                (0,) + O.dp_dense_at((labels, edges), q, 0, 0, j1=3000), i
+        assert [int(x) for x in res["start_off"]] == [2500, 10, 2990]
+        assert c2.stats()["reruns"] >= 3
+    finally:
+        graph.close()
+        c2.close()
