@@ -98,6 +98,29 @@ def recorded_traffic(workload: str, lanes: int):
     return None, None
 
 
+def compare_mode(ctx, graph, batch, out, n, bases, res_exact, stream, ev, o, params):
+    """One warm and one timed alignment launch of the resident (packed)
+    batch in another mode; its distances against the exact ones."""
+    import torch
+    from paper_2206_13574_amd import gwfa
+    gwfa.align_dev(ctx, graph, batch, out, o)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    gwfa.align_dev(ctx, graph, batch, out, o)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    res, _, _ = gwfa.fetch(out, n)
+    ok = (res["status"] == 0) & (res_exact["status"] == 0)
+    exc = (res["dist"] - res_exact["dist"])[ok].astype(np.int64)
+    over = exc > 0
+    return dict(params, align_ms=ms, bases_per_s=bases / (ms / 1000.0),
+                frac_reads_over=float(over.mean()) if len(exc) else 0.0,
+                mean_excess=float(exc.mean()) if len(exc) else 0.0,
+                min_excess=int(exc.min()) if len(exc) else 0, not_ok=int((~ok).sum()))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +134,8 @@ def main():
     ap.add_argument("--a-diff", type=int, default=0)
     ap.add_argument("--no-traceback", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the learned / heuristic pruning comparison after the timed steps")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof FETCH/WRITE counters)")
@@ -226,6 +251,23 @@ def main():
         "reruns": st["reruns"] / steps,
         "not_ok": bad,
     }
+    if args.prune == 0 and not args.no_compare:
+        # the metric's comparison: learned pruning (and Algorithm 4) on the same
+        # resident batch, outside the timed steps, against the exact distances
+        from paper_2206_13574_amd import train_prune
+        W = train_prune.load()
+        ctx.mlp_load(W["w_bf16"], W["scale"])
+        line["compare"] = {
+            "learned-prune": compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
+                                          gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=W["tau"],
+                                                    mlp_gate=W["gate"], mlp_period=W["period"],
+                                                    traceback=bool(o.traceback)),
+                                          dict(tau=W["tau"], gate=W["gate"], period=W["period"])),
+            "heuristic-prune": compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
+                                            gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=50,
+                                                      traceback=bool(o.traceback)), dict(a_diff=50)),
+            "exact_align_ms": align_avg_s * 1000.0,
+        }
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(g, r, seconds=args.cpu_seconds)
