@@ -173,6 +173,13 @@ int gwfa_align_batch(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, const 
                      const int64_t *read_off, const int32_t *v_start, const gwfa_opts *opts,
                      gwfa_result *res, int32_t *path_buf, int64_t path_cap, int64_t *path_needed);
 
+/* One query (host buffers): q (qlen ASCII bases) from start vertex v_start
+ * (Definition 2.2, Algorithm 1's distance and Algorithm 6's walk).  The same
+ * as gwfa_align_batch with one query; on GWFA_ERR_PATH_CAP, res->path_len is
+ * the number of ids the walk needs.  Synchronous. */
+int gwfa_align(gwfa_ctx *ctx, const gwfa_graph *g, const uint8_t *q, int32_t qlen, int32_t v_start,
+               const gwfa_opts *opts, gwfa_result *res, int32_t *path_buf, int64_t path_cap);
+
 /* The same on device-resident inputs (the form the Python binding uses).
  *   d_packed   packed queries (gwfa_pack_dev layout, 2-word zero tail);
  *   d_read_off n_reads+1 int64 base offsets; d_v_start n_reads int32;

@@ -660,6 +660,13 @@ int gwfa_align_batch(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     return out_rc;
 }
 
+int gwfa_align(gwfa_ctx* ctx, const gwfa_graph* g, const uint8_t* q, int32_t qlen, int32_t v_start,
+               const gwfa_opts* opts, gwfa_result* res, int32_t* path_buf, int64_t path_cap) {
+    if (qlen < 0 || !res) return GWFA_ERR_ARG;
+    const int64_t off[2] = {0, qlen};
+    return gwfa_align_batch(ctx, g, 1, q, off, &v_start, opts, res, path_buf, path_cap, nullptr);
+}
+
 int gwfa_mlp_load(gwfa_ctx* ctx, const uint16_t* w, int64_t n, const float* scale) {
     if (!ctx || !w || !scale || n != 4801) return GWFA_ERR_ARG;
     HIPCHK(ctx, hipSetDevice(ctx->device));

@@ -60,6 +60,7 @@ _SIGS = {
     "gwfa_pack_dev": (ctypes.c_int, [_P, _P, _i64, _P, _P, _P]),
     "gwfa_packed_words": (_i64, [_i64]),
     "gwfa_align_batch": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64, _P]),
+    "gwfa_align": (ctypes.c_int, [_P, _P, _P, _i32, _i32, ctypes.POINTER(Opts), _P, _P, _i64]),
     "gwfa_align_batch_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
                                             _P, _P]),
     "gwfa_align_global_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
@@ -346,6 +347,25 @@ def align(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_ca
             raise GwfaError(ERR_PATH_CAP, "align", f"needs {used} ids, buffer {path_cap}")
         paths = [path[r["path_off"]:r["path_off"] + r["path_len"]] if r["path_off"] >= 0 else None for r in res]
     return res, paths
+
+
+def align_one(ctx: Context, graph: Graph, q, v_start: int, o: Opts = None, path_cap: int = None):
+    """gwfa_align: one query from host memory.  Returns (code, result, walk)
+    with walk None unless it was traced and fits."""
+    if o is None:
+        o = opts()
+    qa = np.ascontiguousarray(np.frombuffer(q, dtype=np.uint8) if isinstance(q, (bytes, bytearray)) else q,
+                              dtype=np.uint8)
+    if path_cap is None:
+        path_cap = len(qa) + 64
+    res = np.zeros(1, dtype=RESULT_DTYPE)
+    path = np.zeros(max(path_cap, 1), dtype=np.int32)
+    code = _lib.gwfa_align(ctx.h, graph.h, _np_ptr(qa), len(qa), int(v_start), ctypes.byref(o), _np_ptr(res),
+                           _np_ptr(path) if path_cap > 0 else None, int(path_cap))
+    walk = None
+    if code == OK and o.traceback and res[0]["path_off"] >= 0:
+        walk = path[res[0]["path_off"]:res[0]["path_off"] + res[0]["path_len"]].copy()
+    return code, res[0], walk
 
 
 def align_host(ctx: Context, graph: Graph, seq, off, v_start, o: Opts = None, path_cap: int = 0):
