@@ -22,7 +22,8 @@ import numpy as np
 
 from . import gwfa, synth, train_prune, tune
 
-WORKLOADS = {"cfg1": synth.cfg1, "cfg2": synth.cfg2, "cfg3": synth.cfg3, "cfg4": synth.cfg4}
+WORKLOADS = {"cfg1": synth.cfg1, "cfg2": synth.cfg2, "cfg3": synth.cfg3, "cfg4": synth.cfg4,
+             "cfg4b": lambda: synth.cfg4(sparse=True)}
 
 
 def log(msg):

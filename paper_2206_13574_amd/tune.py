@@ -128,11 +128,11 @@ def main(argv=None):
     import argparse
     from . import synth
     ap = argparse.ArgumentParser(description="autotune the launch shape and arena tiles for a workload")
-    ap.add_argument("--workload", default="cfg2", choices=("cfg1", "cfg2", "cfg3", "cfg4"))
+    ap.add_argument("--workload", default="cfg2", choices=("cfg1", "cfg2", "cfg3", "cfg4", "cfg4b"))
     ap.add_argument("--sample", type=int, default=0, help="queries to time (0: all)")
     ap.add_argument("--repeats", type=int, default=2)
     a = ap.parse_args(argv)
-    g, r = getattr(synth, a.workload)()
+    g, r = synth.cfg4(sparse=True) if a.workload == "cfg4b" else getattr(synth, a.workload)()
     autotune(a.workload, g, r, sample=a.sample, repeats=a.repeats, log=lambda m: print(m, flush=True))
 
 
