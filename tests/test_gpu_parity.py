@@ -280,3 +280,19 @@ def test_full_cfg3_sampled(G):
     g, r = synth.cfg3()
     say(f"cfg3 full: {r.n} reads x 100 kb, graph {g.n_vtx} V (cyclic)")
     _full_size(gw, ctx, g, r, n_sample=4, seed=8, rescore=16)
+
+
+def test_full_cfg4_sampled(gpu_lib):
+    """The 10 Mb bubble graph with all 50,000 reads (10-30 kb, 1-10% error)
+    in its tuned launch configuration: every status OK, distances within the
+    injected edits, sampled reads bit-exact against the capped oracle."""
+    from paper_2206_13574_amd import tune
+    gw = gpu_lib
+    g, r = synth.cfg4()
+    say(f"cfg4 full: {r.n} reads, {int(r.off[-1])} bases, graph {g.n_vtx} V")
+    ctx = gw.Context(0)
+    try:
+        ctx.config(**tune.best_config("cfg4"))
+        _full_size(gw, ctx, g, r, n_sample=3, seed=9, rescore=16)
+    finally:
+        ctx.close()
