@@ -21,6 +21,9 @@
  *   orc_ed_banded   The same restricted to |i-j| <= D (exact when ED <= D).
  *   orc_dp_dense_global  The same rows; the answer is the cell
  *                   H_{|q|, v_e, |v_e|} (the global form with an end vertex).
+ *   orc_dp_dense_clip  The same with a free end gap in the query (up to e
+ *                   trailing bases left unaligned at no cost): the best
+ *                   over rows |q| - e .. |q|.
  *   orc_dp_dense_at Either form with the walk starting after the first j0
  *                   bases of v_s: the initial condition moves to
  *                   H_{0, v_s, j0} = 0 (a read seeded inside a vertex); with
@@ -165,9 +168,12 @@ static void row_answer(const ograph *g, const int32_t *h, int32_t v_s, int32_t j
 
 /* out[0]=d*, out[1]=end vertex, out[2]=end offset j, out[3]=max sweeps in a row.
  * Returns 0, or -1 on allocation failure / non-convergence. */
+/* Called with every finished row i >= row_lo (after its fixpoint). */
+typedef void (*row_fn)(void *cb, const ograph *g, int32_t i, const int32_t *h);
+
 /* Rows 0..|q| of Eq. 1; returns the last row (caller frees) or NULL. */
-static int32_t *dense_last_row(const ograph *g, const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0,
-                               int32_t j1, int *maxsw_out)
+static int32_t *dense_rows(const ograph *g, const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0,
+                           int32_t j1, int32_t row_lo, row_fn fn, void *cb, int *maxsw_out)
 {
     int32_t n = g->n;
     const uint8_t *seq = g->seq;
@@ -184,6 +190,7 @@ static int32_t *dense_last_row(const ograph *g, const uint8_t *q, int32_t qlen, 
     for (int32_t j = j0; j <= j1; j++) prev[g->base[v_s] + j] = 0;
     int sw = row_fixpoint(g, prev);
     if (sw < 0) rc = -1; else if (sw > maxsw) maxsw = sw;
+    if (rc == 0 && fn && row_lo <= 0) fn(cb, g, 0, prev);
     for (int32_t i = 1; i <= qlen && rc == 0; i++) {
         uint8_t qi = up(q[i - 1]);
         for (int32_t v = 0; v < n; v++) {
@@ -201,12 +208,43 @@ static int32_t *dense_last_row(const ograph *g, const uint8_t *q, int32_t qlen, 
         }
         sw = row_fixpoint(g, cur);
         if (sw < 0) rc = -1; else if (sw > maxsw) maxsw = sw;
+        if (rc == 0 && fn && i >= row_lo) fn(cb, g, i, cur);
         int32_t *t = prev; prev = cur; cur = t;
     }
     free(cur);
     if (rc) { free(prev); return NULL; }
     *maxsw_out = maxsw;
     return prev;
+}
+
+static int32_t *dense_last_row(const ograph *g, const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0,
+                               int32_t j1, int *maxsw_out)
+{
+    return dense_rows(g, q, qlen, v_s, j0, j1, qlen + 1, NULL, NULL, maxsw_out);
+}
+
+/* Free end gap in the query: the best over rows i >= |q| - e (the last
+ * |q| - i query bases left unaligned at no cost).  The distance is the
+ * smallest row value; among rows that reach it the largest i wins (the
+ * fewest unaligned bases), then the row's own end rule. */
+typedef struct {
+    int32_t v_s, j0, v_e;
+    int32_t d, ev, ej, i;     /* best so far; d = INF_H: none */
+} clip_best;
+
+static void clip_row(void *cbv, const ograph *g, int32_t i, const int32_t *h)
+{
+    clip_best *cb = (clip_best *)cbv;
+    int32_t o[3];
+    if (cb->v_e >= 0) {
+        int32_t Le = (int32_t)vlen(g, cb->v_e);
+        o[0] = h[g->base[cb->v_e] + Le]; o[1] = cb->v_e; o[2] = Le;
+    } else {
+        row_answer(g, h, cb->v_s, cb->j0, o);
+    }
+    if (o[0] < INF_H && o[0] <= cb->d) {   /* rows come in increasing i: ties go to the later row */
+        cb->d = o[0]; cb->ev = o[1]; cb->ej = o[2]; cb->i = i;
+    }
 }
 
 int orc_dp_dense(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
@@ -246,6 +284,32 @@ int orc_dp_dense_at(int32_t n, const uint8_t *seq, const int64_t *off, int64_t n
         out[0] = h >= INF_H ? -1 : h; out[1] = v_e; out[2] = (int32_t)vlen(&g, v_e);
     }
     out[3] = maxsw;
+    free(last); graph_free(&g);
+    return 0;
+}
+
+/* orc_dp_dense_at with a free end gap of up to e query bases (0 <= e <=
+ * |q|): out[0] = distance (-1 when the global form's end vertex is
+ * unreachable), out[1..2] = end (v, j), out[3] = |q| - i of the chosen row
+ * (query bases left unaligned). */
+int orc_dp_dense_clip(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
+                      const int32_t *src, const int32_t *dst,
+                      const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t j1, int32_t v_e,
+                      int32_t e, int32_t *out)
+{
+    ograph g;
+    if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
+    if (j1 < 0) j1 = j0;
+    if (v_s < 0 || v_s >= n || v_e >= n || j0 < 0 || j1 < j0 || j1 > vlen(&g, v_s) || e < 0 || e > qlen) {
+        graph_free(&g);
+        return -1;
+    }
+    clip_best cb = {v_s, j0, v_e, INF_H, -1, -1, -1};
+    int maxsw = 0;
+    int32_t *last = dense_rows(&g, q, qlen, v_s, j0, j1, qlen - e, clip_row, &cb, &maxsw);
+    if (!last) { graph_free(&g); return -1; }
+    if (cb.d >= INF_H) { out[0] = -1; out[1] = v_e; out[2] = v_e >= 0 ? (int32_t)vlen(&g, v_e) : -1; out[3] = 0; }
+    else { out[0] = cb.d; out[1] = cb.ev; out[2] = cb.ej; out[3] = qlen - cb.i; }
     free(last); graph_free(&g);
     return 0;
 }
@@ -565,24 +629,32 @@ static int dq_push(dqueue *q, int32_t v, int32_t k)
  *               expansion (the paper places it between its d <- d+1 and the
  *               call to the expansion).
  *   max_score   stop with status 1 when d exceeds it (-1: unbounded).
- * out[0] = distance (-1 when stopped), out[1..2] = end (v, j), out[3] = status.
+ *   e_free      free end gap in the query: the end test takes any row
+ *               i >= |q| - e_free (0: the whole query).
+ * out[0] = distance (-1 when stopped), out[1..2] = end (v, j), out[3] = status,
+ * out[4] = query bases left unaligned.
  * work[0] = sum over scores of |F_s| (entries after extension, before
  * pruning); work[1] = number of diagonals ever created (size of H~);
  * work[2] = crossings admitted.  counts (optional) receives |F_s| for
  * s < counts_cap. */
 int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
             const int32_t *src, const int32_t *dst,
-            const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t j1, int32_t v_e, int32_t a_diff,
-            int32_t max_score, int32_t *out, int64_t *work, int32_t *counts, int32_t counts_cap)
+            const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t j1, int32_t v_e, int32_t e_free,
+            int32_t a_diff, int32_t max_score, int32_t *out, int64_t *work, int32_t *counts, int32_t counts_cap)
 {
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
     if (j1 < 0) j1 = j0;
-    if (v_s < 0 || v_s >= n || v_e >= n || j0 < 0 || j1 < j0 || j1 > vlen(&g, v_s)) { graph_free(&g); return -1; }
+    if (v_s < 0 || v_s >= n || v_e >= n || j0 < 0 || j1 < j0 || j1 > vlen(&g, v_s) || e_free < 0 ||
+        e_free > qlen) {
+        graph_free(&g);
+        return -1;
+    }
+    const int32_t i_lo = qlen - e_free;   /* end rows: i_lo .. |q| */
     hmap H = {0, 0, 0};
     dqueue Q = {0}, Qn = {0}, X = {0};
     int rc = 0;
-    out[0] = -1; out[1] = -1; out[2] = -1; out[3] = 0;
+    out[0] = -1; out[1] = -1; out[2] = -1; out[3] = 0; out[4] = 0;
     work[0] = work[1] = work[2] = 0;
     if (hm_grow(&H)) { rc = -1; goto done; }
 
@@ -645,24 +717,35 @@ int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
          * of the end cell (v_e, |q| - |v_e|) has reached offset |v_e|.  An
          * empty wavefront means v_e cannot be reached (out[3] = 2). */
         if (v_e >= 0) {
-            int32_t Le = (int32_t)vlen(&g, v_e);
-            hent *e = hm_find(&H, dkey(v_e, qlen - Le));
-            if (e && e->off == Le) { out[0] = d; out[1] = v_e; out[2] = Le; break; }
+            /* with a free end gap, the cell (i, v_e, |v_e|) of the largest
+             * i >= |q| - e_free that has been reached */
+            int32_t Le = (int32_t)vlen(&g, v_e), hit = -1;
+            for (int32_t i = qlen; i >= i_lo && hit < 0; i--) {
+                hent *e = hm_find(&H, dkey(v_e, i - Le));
+                if (e && e->off == Le) hit = i;
+            }
+            if (hit >= 0) { out[0] = d; out[1] = v_e; out[2] = Le; out[4] = qlen - hit; break; }
             if (Qn.n == 0) { out[3] = 2; break; }
         }
         /* ---- end test (extension mode): some wavefront cell has consumed
          * the whole query. */
         if (v_e < 0) {
-            int found = 0; int32_t bv = -1, bj = -1;
+            /* the largest i >= |q| - e_free over the front cells, then the
+             * smallest (v, j) among that row's end cells */
+            int32_t imax = -1, bv = -1, bj = -1;
             for (int64_t p = 0; p < Qn.n; p++) {
+                hent *e = hm_find(&H, dkey(Qn.v[p], Qn.k[p]));
+                int32_t i = Qn.k[p] + e->off;
+                if (i >= i_lo && i > imax) imax = i;
+            }
+            for (int64_t p = 0; p < Qn.n && imax >= 0; p++) {
                 int32_t v = Qn.v[p], k = Qn.k[p];
                 hent *e = hm_find(&H, dkey(v, k));
-                if (k + e->off != qlen) continue;
-                found = 1;
+                if (k + e->off != imax) continue;
                 if (e->off == 0 && !(v == v_s && j0 == 0)) continue;
                 if (bv < 0 || v < bv || (v == bv && e->off < bj)) { bv = v; bj = e->off; }
             }
-            if (found) { out[0] = d; out[1] = bv; out[2] = bj; break; }
+            if (imax >= 0) { out[0] = d; out[1] = bv; out[2] = bj; out[4] = qlen - imax; break; }
         }
 
         /* ---- Algorithm 4 (pruning) on the extended wavefront */

@@ -294,3 +294,25 @@ def random_gfa(rng, n_seg=8, max_len=6, n_links=12, extras=True):
     order = rng.permutation(len(recs))
     body = "\n".join(recs[i] for i in order)
     return "H\tVN:Z:1.0\n" + body + ("\n" if rng.random() < 0.5 else "")
+
+
+def brute_force_clip(labels, edges, q: bytes, v_s: int, e: int, j0: int = 0, j1: int = None):
+    """A free end gap of up to e query bases: walk enumeration for every
+    query prefix q[:i], i >= |q| - e.  Returns (d*, end set of the largest i
+    reaching d*, |q| - that i)."""
+    best = None
+    for i in range(len(q), len(q) - e - 1, -1):
+        d, ends = brute_force(labels, edges, q[:i], v_s, j0, j1)
+        if best is None or d < best[0]:
+            best = (d, ends, len(q) - i)
+    return best
+
+
+def brute_force_global_clip(labels, edges, q: bytes, v_s: int, v_e: int, e: int, j0: int = 0, j1: int = None):
+    """Global form with a free end gap: (d, clip), (-1, 0) when unreachable."""
+    best = (-1, 0)
+    for i in range(len(q), len(q) - e - 1, -1):
+        d = brute_force_global(labels, edges, q[:i], v_s, v_e, j0, j1)
+        if d >= 0 and (best[0] < 0 or d < best[0]):
+            best = (d, len(q) - i)
+    return best

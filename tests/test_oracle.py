@@ -512,3 +512,63 @@ def test_start_window_is_the_minimum_over_its_starts():
         g = (labels, edges)
         d = O.dp_dense_at(g, q, v_s, j0, j1=j1)[0]
         assert d == min(O.dp_dense_at(g, q, v_s, j)[0] for j in range(j0, j1 + 1)), case
+
+
+# ---------------------------------------------------------------------------
+# a free end gap in the query: up to e trailing bases left unaligned
+# ---------------------------------------------------------------------------
+def test_query_end_gap_hand_cases():
+    g = (["ACGT", "TT"], [(0, 1)])
+    q = b"ACGTTGGG"
+    # e = 0: ACGTT then three insertions, tied with a mismatch + two
+    # insertions against ACGTTT; the smaller end cell wins
+    assert O.dp_dense_clip(g, q, 0, 0) == (3, 1, 1, 0)
+    # e = 2: row 6 (ACGTTG) costs 1 (an insertion after ACGTT)
+    assert O.dp_dense_clip(g, q, 0, 2) == (1, 1, 1, 2)
+    # e >= 3: ACGTT is spelled exactly; clipping more does not help and the
+    # largest such row wins
+    assert O.dp_dense_clip(g, q, 0, 3) == (0, 1, 1, 3) == O.dp_dense_clip(g, q, 0, 8)
+    # global form, end vertex 1 (all of TT): ACGTTG against ACGTTT
+    assert O.dp_dense_clip(g, q, 0, 2, v_e=1) == (1, 1, 2, 2)
+    for e, want in ((0, 0), (2, 2), (3, 3), (8, 3)):
+        assert O.gwf(g, q, 0, e=e)["clip"] == want
+
+
+def test_query_end_gap_brute_force_random_tiny():
+    rng = np.random.default_rng(881)
+    n_clip = 0
+    for case in range(300):
+        labels, edges, q, v_s = refs.random_case(rng, n_vtx=int(rng.integers(1, 5)), max_label=4,
+                                                 p_edge=0.35, qlen=int(rng.integers(0, 8)))
+        e = int(rng.integers(0, len(q) + 1))
+        L = len(labels[v_s])
+        j0 = int(rng.integers(0, L + 1))
+        j1 = int(rng.integers(j0, L + 1)) if rng.random() < 0.3 else j0
+        g = (labels, edges)
+        bd, bends, bclip = refs.brute_force_clip(labels, edges, q, v_s, e, j0, j1)
+        d, ev, ej, clip = O.dp_dense_clip(g, q, v_s, e, j0, j1)
+        n_clip += clip > 0
+        assert (d, clip) == (bd, bclip) and (ev, ej) == min(bends), (case, labels, edges, q, v_s, e, j0, j1)
+        gw = O.gwf(g, q, v_s, j0=j0, j1=j1, e=e)
+        assert (gw["dist"], gw["end_v"], gw["end_j"], gw["clip"]) == (d, ev, ej, clip), case
+        v_e = int(rng.integers(0, len(labels)))
+        wd, wclip = refs.brute_force_global_clip(labels, edges, q, v_s, v_e, e, j0, j1)
+        dg, _, _, cg = O.dp_dense_clip(g, q, v_s, e, j0, j1, v_e)
+        assert (dg, cg if dg >= 0 else 0) == (wd, wclip), (case, v_e)
+        gg = O.gwf(g, q, v_s, v_e=v_e, j0=j0, j1=j1, e=e)
+        assert ((gg["dist"], gg["clip"]) if gg["status"] == 0 else (-1, 0)) == (wd, wclip), case
+    assert n_clip > 50
+
+
+def test_query_end_gap_zero_is_the_plain_form_and_full_gap_is_the_longest_spelled_prefix():
+    rng = np.random.default_rng(882)
+    for case in range(100):
+        labels, edges, q, v_s = refs.random_case(rng, n_vtx=int(rng.integers(1, 6)), max_label=6,
+                                                 p_edge=0.3, qlen=int(rng.integers(0, 14)))
+        g = (labels, edges)
+        assert O.dp_dense_clip(g, q, v_s, 0)[:3] == O.dp_dense_at(g, q, v_s), case
+        # clipping everything: distance 0, keeping the longest prefix of q
+        # that some walk from the start spells exactly
+        d, _, _, clip = O.dp_dense_clip(g, q, v_s, len(q))
+        longest = max(i for i in range(len(q) + 1) if O.dp_dense_at(g, q[:i], v_s)[0] == 0)
+        assert (d, clip) == (0, len(q) - longest), case
