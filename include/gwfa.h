@@ -85,6 +85,11 @@ typedef struct {
                                for every query (GWFA_ERR_VERTEX if out of range) */
     int32_t mlp_gate;       /* learned: run the MLP only when |F_s| >= mlp_gate     */
     int32_t mlp_period;     /* learned: run the MLP every mlp_period scores (>= 1)  */
+    int32_t query_end_free; /* free end gap in the query: up to this many trailing
+                               bases may stay unaligned at no cost (soft clip);
+                               the distance is then the best over query prefixes
+                               of at least |q| - query_end_free bases, ties to the
+                               longest; 0: the whole query is aligned (>= 0)      */
 } gwfa_opts;
 
 typedef struct {
@@ -102,7 +107,8 @@ typedef struct {
     int32_t start_off;      /* bases of the walk's first vertex skipped (the start
                                offset, or where in its start window the traced
                                walk starts; 0 by default)                           */
-    int32_t reserved;       /* 0                                                   */
+    int32_t clip;           /* trailing query bases left unaligned (at most
+                               opts.query_end_free; 0 by default)                  */
 } gwfa_result;              /* 64 bytes */
 
 /* Default options: exact, traceback on, unbounded, extension mode. */
@@ -255,11 +261,12 @@ int gwfa_align_dump_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, con
  * it to a pairwise aligner, noting that it is cheap).  Inputs are the device
  * results and walks of a finished alignment call on the same queries
  * (d_packed, d_read_off as given to it; d_res, d_path_buf as it filled them).
- * For query r whose walk was traced, an optimal global alignment of q and the
- * walk's string (labels of the walk, the first one from start_off, the last
- * one cut at end_off) is written
+ * For query r whose walk was traced, an optimal global alignment of q (its
+ * first |q| - clip bases) and the walk's string (labels of the walk, the
+ * first one from start_off, the last one cut at end_off) is written
  * as CIGAR operations (length << 4 | op, op 7 '=', 8 'X', 1 'I' = query base
- * absent from the walk, 2 'D' = walk base absent from the query) into
+ * absent from the walk, 2 'D' = walk base absent from the query, then
+ * 4 'S' = the clip trailing query bases left unaligned, when clip > 0) into
  * d_cigar (cigar_cap words) at d_cigar_off[r], d_cigar_len[r] operations.
  * Its cost (X + I + D) is the walk's edit distance: the distance for exact
  * alignments, at most the distance under pruning.  d_cigar_len[r] = -1: no

@@ -6,9 +6,11 @@ optional offset inside it and an optional end of a free start window, and
 an optional end segment for the global form.  Give one start for every query
 (--start) or one per query in a tab-separated file (--starts: query name,
 start segment, then optionally offset, window end, end segment; '.' leaves a
-field unset).  Output, one tab-separated line per query: name, length,
-status, distance, end segment, bases of it consumed, start offset, walk
-(oriented segment names), CIGAR of the query against the walk's string.
+field unset).  --query-end-free E lets up to E trailing query bases stay
+unaligned at no cost (a soft clip).  Output, one tab-separated line per
+query: name, length, status, distance, end segment, bases of it consumed,
+start offset, query bases clipped, walk (oriented segment names), CIGAR of
+the query against the walk's string.
 
 Usage:
     python -m paper_2206_13574_amd.align --gfa graph.gfa --reads reads.fa --start s1+ [--cigar] [--out out.tsv]
@@ -72,6 +74,8 @@ def main(argv=None) -> int:
     ap.add_argument("--end", help="oriented end segment for every query (global form)")
     ap.add_argument("--prune", choices=("none", "heuristic", "learned"), default="none")
     ap.add_argument("--a-diff", type=int, default=50)
+    ap.add_argument("--query-end-free", type=int, default=0,
+                    help="trailing query bases that may stay unaligned at no cost")
     ap.add_argument("--cigar", action="store_true", help="also write CIGARs (base-level alignments)")
     ap.add_argument("--forward-only", action="store_true", help="one vertex per segment, + + links only")
     ap.add_argument("--out", default="-")
@@ -115,11 +119,12 @@ def main(argv=None) -> int:
     if a.prune == "learned":
         from . import train_prune
         W = train_prune.load()
-        o = gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=W["tau"], mlp_gate=W["gate"], mlp_period=W["period"])
+        o = gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=W["tau"], mlp_gate=W["gate"], mlp_period=W["period"],
+                      query_end_free=a.query_end_free)
     elif a.prune == "heuristic":
-        o = gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=a.a_diff)
+        o = gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=a.a_diff, query_end_free=a.query_end_free)
     else:
-        o = gwfa.opts()
+        o = gwfa.opts(query_end_free=a.query_end_free)
 
     ctx = gwfa.Context(0)
     graph = gwfa.Graph.of(ctx, gfa.graph)
@@ -147,7 +152,7 @@ def main(argv=None) -> int:
     ctx.close()
 
     fo = sys.stdout if a.out == "-" else open(a.out, "w")
-    fo.write("#name\tlength\tstatus\tdist\tend\tend_off\tstart_off\twalk\tcigar\n")
+    fo.write("#name\tlength\tstatus\tdist\tend\tend_off\tstart_off\tclip\twalk\tcigar\n")
     for i in range(n):
         r = res[i]
         walk = "."
@@ -159,7 +164,7 @@ def main(argv=None) -> int:
             ops, coff, clen = cig
             cg = gwfa.cigar_string(ops[coff[i]:coff[i] + clen[i]]) or "."
         fo.write(f"{names[i]}\t{len(seqs[i])}\t{STATUS.get(int(r['status']), r['status'])}\t{int(r['dist'])}\t"
-                 f"{end}\t{int(r['end_off'])}\t{int(r['start_off'])}\t{walk}\t{cg}\n")
+                 f"{end}\t{int(r['end_off'])}\t{int(r['start_off'])}\t{int(r['clip'])}\t{walk}\t{cg}\n")
     if fo is not sys.stdout:
         fo.close()
     return 0

@@ -14,7 +14,8 @@
 // of T consumed) and is stored at offset s*s of the workgroup's buffer, so a
 // distance d needs (d+1)^2 words.  Operation words are (length << 4) | op
 // with op 7 ('=', match), 8 ('X', mismatch), 1 ('I', query base absent from
-// the walk), 2 ('D', walk base absent from the query), as in SAM/BAM.
+// the walk), 2 ('D', walk base absent from the query), 4 ('S', query bases
+// left unaligned by a free end gap in the query), as in SAM/BAM.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,7 +25,7 @@ namespace gwfa_cig {
 
 typedef unsigned long long ull;
 constexpr int32_t NEG = -(1 << 30);
-constexpr uint32_t OP_EQ = 7, OP_X = 8, OP_I = 1, OP_D = 2;
+constexpr uint32_t OP_EQ = 7, OP_X = 8, OP_I = 1, OP_D = 2, OP_S = 4;
 
 __device__ __forceinline__ ull win32(const ull* __restrict__ w, int64_t p) {
     const int64_t wi = p >> 5;
@@ -87,9 +88,11 @@ __global__ __launch_bounds__(BLOCK) void k_cigar(CigArgs A) {
         if (r >= A.n_reads) break;
         const gwfa_result res = A.res[r];
         const int64_t q0 = A.rd_off[r];
-        const int32_t qlen = (int32_t)(A.rd_off[r + 1] - q0);
+        const int32_t qfull = (int32_t)(A.rd_off[r + 1] - q0);
+        // the graph alignment covers q[0, qfull - clip); the rest is soft-clipped
+        const int32_t qlen = qfull - res.clip;
         if (res.status != GWFA_ST_OK || res.path_off < 0 || res.path_len <= 0 || res.dist > A.max_d ||
-            qlen > A.max_q || res.start_off < 0) {
+            qfull > A.max_q || res.start_off < 0 || res.clip < 0 || qlen < 0) {
             if (tid == 0) { A.cigar_off[r] = -1; A.cigar_len[r] = -1; }
             continue;
         }
@@ -198,6 +201,7 @@ __global__ __launch_bounds__(BLOCK) void k_cigar(CigArgs A) {
                     if (n > 0 && (ops[n - 1] & 15u) == op) ops[n - 1] += (uint32_t)len << 4;
                     else ops[n++] = ((uint32_t)len << 4) | op;
                 };
+                emit(OP_S, qfull - qlen);
                 int32_t k = kend, i = qlen;
                 for (int32_t ss = dd; ss > 0; --ss) {
                     int32_t mis, ins, del;

@@ -35,6 +35,7 @@ struct KArgs {
     int32_t prune, a_diff, traceback, max_score;
     float keep_threshold;
     int32_t mlp_gate, mlp_period;
+    int32_t end_free;                // free end gap in the query (trailing bases)
     const uint16_t* mlp_w;           // bf16 weights (device) or null
     const float* mlp_scale;          // 8 feature scales (device) or null
     float* dump;                     // per-entry trace records (16 x 4 bytes) or null

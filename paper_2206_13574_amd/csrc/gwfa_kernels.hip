@@ -244,6 +244,7 @@ struct Shared {
     int32_t mn;       // trace entries created
     int32_t flags;
     int32_t found;
+    int32_t iend;     // largest end row reached (free end gap in the query)
     int32_t amax;
     int32_t imax;
     int32_t dropped;
@@ -274,6 +275,7 @@ struct Q {
     int32_t qlen, vs;
     int32_t j0, j1;   // start window: the walk starts after the first j bases of vs, j0 <= j <= j1
     int32_t ve;       // end vertex (global form) or -1 (extension mode)
+    int32_t ilo;      // end rows: ilo .. qlen (qlen minus the free end gap in the query)
     ull* dir;
     Page* pages;
     ull* mkey;
@@ -307,10 +309,13 @@ __device__ __forceinline__ int record_entry(const Q& q, Shared& S, int32_t v, in
     if (mark || o == Lv || i == q.qlen) q.pages[d].R[k & 31] = mkR(q.gen, o);
     // end test: extension mode, any cell of the last query row; global form,
     // the cell at the end of the end vertex (Algorithm 1).  Offset-0 cells
-    // end a walk only at the start cell (vs, 0).
-    if (i == q.qlen && (q.ve < 0 || (v == q.ve && o == Lv))) {
+    // end a walk only at the start cell (vs, 0).  With a free end gap in the
+    // query every row from ilo on ends: the largest row reached is found
+    // here, its smallest end cell once the score is complete.
+    if (i >= q.ilo && (q.ve < 0 || (v == q.ve && o == Lv))) {
         S.found = 1;
-        if (q.ve >= 0 || o >= 1 || (v == q.vs && q.j0 == 0))
+        if (q.ilo < q.qlen) atomicMax(&S.iend, i);
+        else if (q.ve >= 0 || o >= 1 || (v == q.vs && q.j0 == 0))
             atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
     }
     if (q.track) {
@@ -449,6 +454,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     q.ve = __builtin_amdgcn_readfirstlane(A.v_end ? A.v_end[r] : A.end_vertex);
     q.j0 = __builtin_amdgcn_readfirstlane(A.v_off ? A.v_off[r] : 0);
     q.j1 = __builtin_amdgcn_readfirstlane(A.v_off_hi ? A.v_off_hi[r] : q.j0);
+    q.ilo = max(0, q.qlen - A.end_free);
     gwfa_result* out = A.res + r;
     const int64_t t_begin = (int64_t)wall_clock64();
     const int64_t* __restrict__ seg_off = A.seg_off;
@@ -460,7 +466,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             out->t_begin = t_begin; out->t_end = t_begin;
             out->dist = -1; out->end_v = -1; out->end_off = -1; out->status = GWFA_ST_BAD_INPUT;
             out->path_off = -1; out->path_len = 0; out->n_scores = 0; out->work = 0;
-            out->start_off = q.j0; out->reserved = 0;
+            out->start_off = q.j0; out->clip = 0;
         }
         return;
     }
@@ -498,6 +504,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     }
     int status = -1;
     int32_t s = 0;
+    int32_t clip = 0;         // query bases left unaligned (free end gap)
     int cur = 1;
     int32_t n_cur = 0;
     int32_t vmx = 0;          // crossing entries of the source list merged virtually
@@ -517,7 +524,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             S.gen = g;
             S.n_out = 0; S.ncand = 0; S.dirn = 0; S.mn = 0; S.flags = 0;
             S.chunks = 0; S.cross = 0; S.adm = 0; S.mlp = 0; S.dropped = 0;
-            S.found = 0; S.endkey = ~0ull; S.amax = 0; S.imax = 0;
+            S.found = 0; S.iend = -1; S.endkey = ~0ull; S.amax = 0; S.imax = 0;
             S.tick[0] = S.tick[1] = S.tick[2] = S.tick[3] = 0;
         }
         __syncthreads();
@@ -563,7 +570,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             int32_t n1 = 0;           // diagonals produced by the expansion
             ull tk = wall_clock64();
             if (s > 0) {
-                if (tid == 0) { S.found = 0; S.endkey = ~0ull; S.amax = 0; S.imax = 0; }
+                if (tid == 0) { S.found = 0; S.iend = -1; S.endkey = ~0ull; S.amax = 0; S.imax = 0; }
                 __syncthreads();
                 // ========== EXPAND (Algorithm 3) + EXTEND of what it admits ==========
                 const Lists Ls = LL(cur);
@@ -912,18 +919,30 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             work += ntot;
             __syncthreads();
             const int found = __builtin_amdgcn_readfirstlane(S.found);
+            const int32_t iend = q.ilo < q.qlen ? __builtin_amdgcn_readfirstlane(S.iend) : q.qlen;
             const int32_t amax = __builtin_amdgcn_readfirstlane(S.amax);
             const int32_t imax = __builtin_amdgcn_readfirstlane(S.imax);
             __syncthreads();
             // ========== end test (extension mode) ==========
             if (found) {
                 status = GWFA_ST_OK;
+                clip = q.qlen - iend;
+                if (q.ilo < q.qlen) {
+                    // the end cells of row iend (all of them are in this score's list)
+                    for (int32_t idx = tid; idx < ntot; idx += BLOCK) {
+                        const int32_t v = Ld.v[idx], o = Ld.o[idx];
+                        if (Ld.k[idx] + o != iend) continue;
+                        if (q.ve >= 0 ? (v == q.ve && o == Ld.l[idx]) : (o >= 1 || (v == q.vs && q.j0 == 0)))
+                            atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
+                    }
+                    __syncthreads();
+                }
                 if (q.tb) {
                     if (tid == 0) S.tend = -1;
                     __syncthreads();
                     const int32_t ev = (int32_t)(S.endkey >> 32), eo = (int32_t)(S.endkey & 0xffffffffull);
                     for (int32_t idx = tid; idx < ntot; idx += BLOCK)
-                        if (Ld.v[idx] == ev && Ld.o[idx] == eo && Ld.k[idx] + eo == q.qlen) S.tend = Ld.t[idx];
+                        if (Ld.v[idx] == ev && Ld.o[idx] == eo && Ld.k[idx] + eo == iend) S.tend = Ld.t[idx];
                     __syncthreads();
                 }
                 break;
@@ -1119,7 +1138,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
         out->path_off = -1;
         out->path_len = 0;
         out->start_off = q.j0;
-        out->reserved = 0;
+        out->clip = clip;
         if (status == GWFA_ST_OK) {
             out->dist = s;
             out->end_v = (int32_t)(S.endkey >> 32);

@@ -35,14 +35,14 @@ PRUNE_NONE, PRUNE_HEURISTIC, PRUNE_LEARNED = 0, 1, 2
 
 RESULT_DTYPE = np.dtype([("dist", "<i4"), ("end_v", "<i4"), ("end_off", "<i4"), ("status", "<i4"),
                          ("path_off", "<i8"), ("path_len", "<i4"), ("n_scores", "<i4"), ("work", "<i8"),
-                         ("t_begin", "<i8"), ("t_end", "<i8"), ("start_off", "<i4"), ("reserved", "<i4")])
+                         ("t_begin", "<i8"), ("t_end", "<i8"), ("start_off", "<i4"), ("clip", "<i4")])
 assert RESULT_DTYPE.itemsize == 64
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("prune", ctypes.c_int32), ("a_diff", ctypes.c_int32), ("keep_threshold", ctypes.c_float),
                 ("traceback", ctypes.c_int32), ("max_score", ctypes.c_int32), ("end_vertex", ctypes.c_int32),
-                ("mlp_gate", ctypes.c_int32), ("mlp_period", ctypes.c_int32)]
+                ("mlp_gate", ctypes.c_int32), ("mlp_period", ctypes.c_int32), ("query_end_free", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -130,12 +130,14 @@ def exported_symbols():
 
 
 def opts(prune: int = PRUNE_NONE, a_diff: int = 0, keep_threshold: float = 0.0, traceback: bool = True,
-         max_score: int = -1, end_vertex: int = -1, mlp_gate: int = 0, mlp_period: int = 1) -> Opts:
+         max_score: int = -1, end_vertex: int = -1, mlp_gate: int = 0, mlp_period: int = 1,
+         query_end_free: int = 0) -> Opts:
     o = Opts()
     _lib.gwfa_opts_default(ctypes.byref(o))
     o.prune, o.a_diff, o.keep_threshold = int(prune), int(a_diff), float(keep_threshold)
     o.traceback, o.max_score, o.end_vertex = int(bool(traceback)), int(max_score), int(end_vertex)
     o.mlp_gate, o.mlp_period = int(mlp_gate), int(mlp_period)
+    o.query_end_free = int(query_end_free)
     return o
 
 
@@ -539,7 +541,7 @@ class Plan:
             pass
 
 
-CIGAR_OPS = {7: "=", 8: "X", 1: "I", 2: "D"}
+CIGAR_OPS = {7: "=", 8: "X", 1: "I", 2: "D", 4: "S"}
 
 
 def cigar_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, cigar_cap: int = None):

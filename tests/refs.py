@@ -210,19 +210,24 @@ def _brute_force_global(labels, edges, q: bytes, v_s: int, v_e: int, j0: int = 0
     return best[0]
 
 
-CIGAR_OPS = {7: "=", 8: "X", 1: "I", 2: "D"}
+CIGAR_OPS = {7: "=", 8: "X", 1: "I", 2: "D", 4: "S"}
 
 
 def cigar_cost(q: bytes, t: bytes, ops) -> int:
     """Checks that CIGAR words (length << 4 | op) align q to t exactly (every
     '=' pairs equal bases, every 'X' unequal ones, all of both strings
-    consumed) and returns the alignment's cost X + I + D."""
+    consumed) and returns the alignment's cost X + I + D.  A soft clip 'S'
+    (query bases left unaligned) may only come last and costs nothing."""
     q, t = q.upper(), t.upper()
     i = j = cost = 0
-    for w in ops:
+    ops = list(ops)
+    for x, w in enumerate(ops):
         n, op = int(w) >> 4, CIGAR_OPS[int(w) & 15]
         assert n > 0
-        if op == "=":
+        if op == "S":
+            assert x == len(ops) - 1
+            i += n
+        elif op == "=":
             assert q[i:i + n] == t[j:j + n]
             i += n; j += n
         elif op == "X":
