@@ -236,6 +236,8 @@ class DeviceBatch:
 def upload_reads(ctx: Context, seq: np.ndarray, off: np.ndarray, v_start: np.ndarray) -> DeviceBatch:
     torch = ctx.torch
     seq = np.ascontiguousarray(seq, dtype=np.uint8)
+    if not seq.flags.writeable:          # a view of bytes: torch wants writable memory
+        seq = seq.copy()
     off = np.ascontiguousarray(off, dtype=np.int64)
     vs = np.ascontiguousarray(v_start, dtype=np.int32)
     n = len(vs)
