@@ -160,7 +160,7 @@ void gwfa_graph_destroy(gwfa_graph *g);
  * gwfa_packed_words(n_bases) words: the 2-word zero tail is written too) on
  * `hip_stream` (NULL = the context's stream).  A base outside ACGT/acgt sets
  * *d_err (device int32, the caller clears it first) to GWFA_ERR_ALPHABET;
- * such bases are packed as A.  Asynchronous. */
+ * the packed words are then unspecified.  Asynchronous. */
 int gwfa_pack_dev(gwfa_ctx *ctx, const uint8_t *d_ascii, int64_t n_bases, uint64_t *d_packed,
                   int32_t *d_err, void *hip_stream);
 int64_t gwfa_packed_words(int64_t n_bases);
