@@ -321,3 +321,47 @@ def brute_force_global_clip(labels, edges, q: bytes, v_s: int, v_e: int, e: int,
         if d >= 0 and (best[0] < 0 or d < best[0]):
             best = (d, len(q) - i)
     return best
+
+
+def mutate(rng, s: bytes, err: float) -> bytes:
+    """Substitutions, insertions and deletions, each at rate err/3 per base."""
+    out = bytearray()
+    for c in s:
+        r = rng.random()
+        if r < err / 3:
+            out.append(b"ACGT"[(b"ACGT".index(c) + 1 + int(rng.integers(0, 3))) % 4])
+        elif r < 2 * err / 3:
+            out.append(c)
+            out.append(b"ACGT"[int(rng.integers(0, 4))])
+        elif r < err:
+            pass
+        else:
+            out.append(c)
+    return bytes(out)
+
+
+def medium_case(rng):
+    """A 20-200 vertex graph (labels mostly 1-8 bases, some up to 400; a
+    backbone chain, skip edges forming bubbles, back edges and self-loops
+    forming cycles) and a query spelled along a random walk of 50-3,000 bases
+    with 0-12% errors.  Returns (labels, edges, q, v_s, last vertex of the
+    walk)."""
+    n = int(rng.integers(20, 200))
+    lens = []
+    for _ in range(n):
+        u = rng.random()
+        lens.append(int(rng.integers(1, 9)) if u < 0.7 else
+                    (int(rng.integers(9, 61)) if u < 0.95 else int(rng.integers(61, 401))))
+    labels = ["".join("ACGT"[x] for x in rng.integers(0, 4, size=L)) for L in lens]
+    edges = set((a, a + 1) for a in range(n - 1))
+    for a in range(n):
+        if rng.random() < 0.3 and a + 2 < n:
+            edges.add((a, int(rng.integers(a + 2, min(n, a + 6)))))
+        if rng.random() < 0.08 and a > 0:
+            edges.add((a, int(rng.integers(max(0, a - 30), a))))
+        if rng.random() < 0.03:
+            edges.add((a, a))
+    edges = sorted(edges)
+    vs = int(rng.integers(0, n // 2))
+    t, walk = spell_random_walk(rng, labels, edges, vs, int(rng.integers(50, 3000)))
+    return labels, edges, mutate(rng, t, float(rng.uniform(0.0, 0.12))), vs, walk[-1]

@@ -1,0 +1,109 @@
+"""GPU parity on medium random graphs, between the tiny-graph tests and the
+full workloads: 20-200 vertices with labels of 1-400 bases, bubbles, back
+edges and self-loops (cycles), queries of 50-3,000 bases spelled along random
+walks with 0-12% errors, so that wavefronts span several batches of the
+workgroup and crossings go around cycles.  Exact runs in both forms:
+distance, end and work bit-exact against the dense oracle and the
+Algorithms 1-4 transcription, walks re-scored; Algorithm 4 against its
+transcription; CIGARs re-scored."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import refs
+from tests.test_gpu_parity import union_graph, reads_of
+
+pytestmark = pytest.mark.gpu
+
+N_CASES = 150
+
+
+def say(msg):
+    print(f"[gpu-medium] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def G(gpu_lib):
+    ctx = gpu_lib.Context(0)
+    yield gpu_lib, ctx
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def cases():
+    rng = np.random.default_rng(8100)
+    cs = [refs.medium_case(rng) for _ in range(N_CASES)]
+    g, base = union_graph([c[:4] for c in cs])
+    return cs, g, base
+
+
+def _run(gw, ctx, g, base, cs, o, form, cigar=False):
+    graph = gw.Graph.of(ctx, g)
+    try:
+        seq, off = reads_of([c[2] for c in cs])
+        n = len(cs)
+        batch = gw.upload_reads(ctx, seq, off, np.array([c[3] + b for c, b in zip(cs, base)], np.int32))
+        out = gw.alloc_out(ctx, n, int(off[-1]) * 4 + 256 * n)
+        ve = None
+        if form == "global":
+            ve = ctx.torch.from_numpy(np.array([c[4] + b for c, b in zip(cs, base)], np.int32)).to(ctx.tdev)
+        gw.step_dev(ctx, graph, batch, out, o, ve)
+        res, path, _ = gw.fetch(out, n)
+        cig = gw.cigar_dev(ctx, graph, batch, out) if cigar else None
+        return res, path, cig
+    finally:
+        graph.close()
+
+
+@pytest.mark.parametrize("form", ["extension", "global"])
+def test_medium_exact(G, cases, form):
+    gw, ctx = G
+    cs, g, base = cases
+    say(f"{form}: {len(cs)} medium graphs, exact")
+    res, path, _ = _run(gw, ctx, g, base, cs, gw.opts(), form)
+    for i, (labels, edges, q, vs, vl) in enumerate(cs):
+        ve = vl if form == "global" else -1
+        d, ev, ej = O.dp_dense_at((labels, edges), q, vs, 0, ve)
+        wf = O.gwf((labels, edges), q, vs, v_e=ve)
+        r = res[i]
+        assert (r["status"], r["dist"], r["end_v"] - base[i], r["end_off"], r["work"]) == \
+            (0, d, ev, ej, wf["work"]), (form, i)
+        p = path[r["path_off"]:r["path_off"] + r["path_len"]]
+        assert p[0] == vs + base[i] and p[-1] == ev + base[i] and O.is_walk(g, p)
+        assert O.ed_global(q, O.spell_walk(g, p, ej)) == d
+
+
+@pytest.mark.parametrize("form", ["extension", "global"])
+def test_medium_algorithm_4(G, cases, form):
+    gw, ctx = G
+    cs, g, base = cases
+    a = 20
+    say(f"{form}: {len(cs)} medium graphs, Algorithm 4 a_diff {a}")
+    res, path, _ = _run(gw, ctx, g, base, cs, gw.opts(prune=gw.PRUNE_HEURISTIC, a_diff=a), form)
+    for i, (labels, edges, q, vs, vl) in enumerate(cs):
+        ve = vl if form == "global" else -1
+        wf = O.gwf((labels, edges), q, vs, v_e=ve, a_diff=a)
+        r = res[i]
+        if wf["status"] != 0:        # pruning emptied the wavefront before the end vertex
+            assert wf["status"] == 2 and r["status"] == gw.ST_UNREACHABLE, (form, i)
+            continue
+        assert (r["dist"], r["end_v"] - base[i], r["end_off"], r["work"]) == \
+            (wf["dist"], wf["end_v"], wf["end_j"], wf["work"]), (form, i)
+        # the walk is a witness: its best alignment costs between d* and the distance
+        p = path[r["path_off"]:r["path_off"] + r["path_len"]]
+        e = O.ed_global(q, O.spell_walk(g, p, int(r["end_off"])))
+        assert O.dp_dense_at((labels, edges), q, vs, 0, ve)[0] <= e <= r["dist"], (form, i)
+
+
+@pytest.mark.parametrize("form", ["extension", "global"])
+def test_medium_cigar(G, cases, form):
+    gw, ctx = G
+    cs, g, base = cases
+    say(f"{form}: {len(cs)} medium graphs, exact, then CIGARs")
+    res, path, (ops, coff, clen) = _run(gw, ctx, g, base, cs, gw.opts(), form, cigar=True)
+    for i, (labels, edges, q, vs, vl) in enumerate(cs):
+        r = res[i]
+        assert r["status"] == 0 and clen[i] >= 0, (form, i)
+        p = path[r["path_off"]:r["path_off"] + r["path_len"]]
+        T = O.spell_walk(g, p, int(r["end_off"]))
+        assert refs.cigar_cost(q, T, ops[coff[i]:coff[i] + clen[i]]) == r["dist"], (form, i)
