@@ -107,3 +107,58 @@ def test_medium_cigar(G, cases, form):
         p = path[r["path_off"]:r["path_off"] + r["path_len"]]
         T = O.spell_walk(g, p, int(r["end_off"]))
         assert refs.cigar_cost(q, T, ops[coff[i]:coff[i] + clen[i]]) == r["dist"], (form, i)
+
+
+@pytest.mark.parametrize("form", ["extension", "global"])
+def test_medium_clip_and_windows(G, form):
+    """Free end gap in the query (e = 40) on the medium graphs with random
+    tails of 0-29 bases appended and, for half the queries, a free start
+    window: distance, end, clip and work bit-exact, the walk starts inside
+    the window, CIGARs end with the clip."""
+    gw, ctx = G
+    rng = np.random.default_rng(8101)
+    cs = []
+    for _ in range(N_CASES):
+        labels, edges, q, vs, vl = refs.medium_case(rng)
+        q = q + bytes(b"ACGT"[x] for x in rng.integers(0, 4, size=int(rng.integers(0, 30))))
+        L = len(labels[vs])
+        j0 = int(rng.integers(0, L + 1)) if rng.random() < 0.5 else 0
+        j1 = int(rng.integers(j0, L + 1)) if rng.random() < 0.5 else j0
+        cs.append((labels, edges, q, vs, vl, j0, j1))
+    g, base = union_graph([c[:4] for c in cs])
+    e = 40
+    say(f"{form}: {len(cs)} medium graphs with tails, e = {e}, start windows, then CIGARs")
+    graph = gw.Graph.of(ctx, g)
+    try:
+        seq, off = reads_of([c[2] for c in cs])
+        n = len(cs)
+        dev = lambda x: ctx.torch.from_numpy(np.ascontiguousarray(x, np.int32)).to(ctx.tdev)
+        batch = gw.upload_reads(ctx, seq, off, np.array([c[3] + b for c, b in zip(cs, base)], np.int32))
+        out = gw.alloc_out(ctx, n, int(off[-1]) * 4 + 256 * n)
+        ve = dev([c[4] + b for c, b in zip(cs, base)]) if form == "global" else None
+        gw.step_dev(ctx, graph, batch, out, gw.opts(query_end_free=e), ve, dev([c[5] for c in cs]),
+                    dev([c[6] for c in cs]))
+        res, path, _ = gw.fetch(out, n)
+        ops, coff, clen = gw.cigar_dev(ctx, graph, batch, out)
+    finally:
+        graph.close()
+    n_clip = 0
+    for i, (labels, edges, q, vs, vl, j0, j1) in enumerate(cs):
+        vee = vl if form == "global" else -1
+        ee = min(e, len(q))
+        d, ev, ej, clip = O.dp_dense_clip((labels, edges), q, vs, ee, j0=j0, j1=j1, v_e=vee)
+        wf = O.gwf((labels, edges), q, vs, j0=j0, j1=j1, v_e=vee, e=ee)
+        r = res[i]
+        assert (r["status"], r["dist"], r["end_v"] - base[i], r["end_off"], r["clip"], r["work"]) == \
+            (0, d, ev, ej, clip, wf["work"]), (form, i)
+        n_clip += clip > 0
+        so = int(r["start_off"])
+        p = path[r["path_off"]:r["path_off"] + r["path_len"]]
+        assert j0 <= so <= j1 and p[0] == vs + base[i] and O.is_walk(g, p)
+        T = O.spell_walk(g, p, ej)[so:]
+        assert O.ed_global(q[:len(q) - clip], T) == d
+        w = ops[coff[i]:coff[i] + clen[i]]
+        assert clen[i] >= 0 and refs.cigar_cost(q, T, w) == d
+        if clip:
+            assert (int(w[-1]) & 15) == 4 and int(w[-1]) >> 4 == clip
+    assert n_clip > N_CASES // 3
