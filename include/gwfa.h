@@ -89,7 +89,9 @@ typedef struct {
                                bases may stay unaligned at no cost (soft clip);
                                the distance is then the best over query prefixes
                                of at least |q| - query_end_free bases, ties to the
-                               longest; 0: the whole query is aligned (>= 0)      */
+                               longest; 0: the whole query is aligned, as in
+                               Definition 2.2, which penalises the query's end
+                               gaps (>= 0; values above |q| act as |q|)            */
 } gwfa_opts;
 
 typedef struct {
