@@ -45,7 +45,7 @@ def _load():
     i32, i64 = ctypes.c_int32, ctypes.c_int64
     lib.orc_dp_dense.argtypes = [i32, P, P, i64, P, P, P, i32, i32, P]
     lib.orc_dp_dense.restype = ctypes.c_int
-    lib.orc_dp_dense_at.argtypes = [i32, P, P, i64, P, P, P, i32, i32, i32, i32, i32, P]
+    lib.orc_dp_dense_at.argtypes = [i32, P, P, i64, P, P, P, i32, i32, i32, i32, i32, i32, P]
     lib.orc_dp_dense_at.restype = ctypes.c_int
     lib.orc_dp_dense_global.argtypes = [i32, P, P, i64, P, P, P, i32, i32, i32, P]
     lib.orc_dp_dense_global.restype = ctypes.c_int
@@ -59,8 +59,8 @@ def _load():
     lib.orc_ed_global.restype = i64
     lib.orc_ed_banded.argtypes = [P, i64, P, i64, i64]
     lib.orc_ed_banded.restype = i64
-    lib.orc_gwf.argtypes = [i32, P, P, i64, P, P, P, i32, i32, i32, i32, i32, i32, i32, i32, P, P, P, i32]
-    lib.orc_dp_dense_clip.argtypes = [i32, P, P, i64, P, P, P, i32, i32, i32, i32, i32, i32, P]
+    lib.orc_gwf.argtypes = [i32, P, P, i64, P, P, P, i32, i32, i32, i32, i32, i32, i32, i32, i32, P, P, P, i32]
+    lib.orc_dp_dense_clip.argtypes = [i32, P, P, i64, P, P, P, i32, i32, i32, i32, i32, i32, i32, P]
     lib.orc_dp_dense_clip.restype = ctypes.c_int
     lib.orc_gwf.restype = ctypes.c_int
     lib.orc_rev_labels.argtypes = [i32, P, P, i64, P, P, P, i32, i32, P, P, P, P, i64, P]
@@ -136,22 +136,23 @@ def dp_dense(g, q, v_s: int):
     return int(out[0]), int(out[1]), int(out[2]), int(out[3])
 
 
-def dp_dense_at(g, q, v_s: int, j0: int = 0, v_e: int = -1, j1: int = -1):
+def dp_dense_at(g, q, v_s: int, j0: int = 0, v_e: int = -1, j1: int = -1, wfree: bool = False):
     """Eq. 1 dense with the walk starting after the first j bases of v_s, j
     free in j0..j1 (j1 = -1: j = j0); extension form (v_e = -1: (d*, end_v,
     end_j)) or global form with end vertex v_e ((d, v_e, |v_e|), d = -1 when
-    unreachable)."""
+    unreachable); wfree: the walk may end anywhere inside v_e ((d, v_e, j))."""
     lib = _load()
     G = OGraph.of(g)
     qq = _u8(q)
     out = np.zeros(4, dtype=np.int32)
-    rc = lib.orc_dp_dense_at(*G._args(), _ptr(qq), len(qq), int(v_s), int(j0), int(j1), int(v_e), _ptr(out))
+    rc = lib.orc_dp_dense_at(*G._args(), _ptr(qq), len(qq), int(v_s), int(j0), int(j1), int(v_e), int(bool(wfree)),
+                             _ptr(out))
     if rc != 0:
         raise RuntimeError("orc_dp_dense_at failed")
     return int(out[0]), int(out[1]), int(out[2])
 
 
-def dp_dense_clip(g, q, v_s: int, e: int, j0: int = 0, j1: int = -1, v_e: int = -1):
+def dp_dense_clip(g, q, v_s: int, e: int, j0: int = 0, j1: int = -1, v_e: int = -1, wfree: bool = False):
     """dp_dense_at with a free end gap of up to e query bases: the best over
     rows |q| - e .. |q| (ties: the largest row).  Returns (d, end_v, end_j,
     clip) with clip = query bases left unaligned; d = -1 when the global
@@ -160,8 +161,8 @@ def dp_dense_clip(g, q, v_s: int, e: int, j0: int = 0, j1: int = -1, v_e: int = 
     G = OGraph.of(g)
     qq = _u8(q)
     out = np.zeros(4, dtype=np.int32)
-    rc = lib.orc_dp_dense_clip(*G._args(), _ptr(qq), len(qq), int(v_s), int(j0), int(j1), int(v_e), int(e),
-                               _ptr(out))
+    rc = lib.orc_dp_dense_clip(*G._args(), _ptr(qq), len(qq), int(v_s), int(j0), int(j1), int(v_e), int(bool(wfree)),
+                               int(e), _ptr(out))
     if rc != 0:
         raise RuntimeError("orc_dp_dense_clip failed")
     return int(out[0]), int(out[1]), int(out[2]), int(out[3])
@@ -230,9 +231,9 @@ def ed_banded(a, b, D: int) -> int:
 
 
 def gwf(g, q, v_s: int, a_diff: int = 0, max_score: int = -1, counts_cap: int = 0, v_e: int = -1, j0: int = 0,
-        j1: int = -1, e: int = 0):
+        j1: int = -1, e: int = 0, wfree: bool = False):
     """Algorithms 1-4 in extension mode (v_e = -1) or in the global form with
-    end vertex v_e; the walk starts after the first j bases of v_s, j free in
+    end vertex v_e (wfree: ending anywhere inside v_e); the walk starts after the first j bases of v_s, j free in
     j0..j1 (j1 = -1: j = j0); up to e trailing query bases may stay unaligned
     (`clip` in the result: how many did).  Returns a dict with dist, end_v, end_j, status (0 ok,
     1 max_score, 2 end vertex unreachable), work (sum |F_s|), diagonals,
@@ -243,7 +244,8 @@ def gwf(g, q, v_s: int, a_diff: int = 0, max_score: int = -1, counts_cap: int = 
     out = np.zeros(5, dtype=np.int32)
     work = np.zeros(3, dtype=np.int64)
     counts = np.zeros(max(counts_cap, 1), dtype=np.int32)
-    rc = lib.orc_gwf(*G._args(), _ptr(qq), len(qq), int(v_s), int(j0), int(j1), int(v_e), int(e), int(a_diff), int(max_score),
+    rc = lib.orc_gwf(*G._args(), _ptr(qq), len(qq), int(v_s), int(j0), int(j1), int(v_e), int(bool(wfree)), int(e),
+                     int(a_diff), int(max_score),
                      _ptr(out), _ptr(work), _ptr(counts) if counts_cap else None, int(counts_cap))
     if rc != 0:
         raise RuntimeError("orc_gwf failed")

@@ -24,6 +24,12 @@
  *   orc_dp_dense_clip  The same with a free end gap in the query (up to e
  *                   trailing bases left unaligned at no cost): the best
  *                   over rows |q| - e .. |q|.
+ *   wfree           (orc_dp_dense_at, orc_dp_dense_clip, orc_gwf) the global
+ *                   form with a free end gap in the walk (one of the
+ *                   variants Section 2.2 points to): the walk may end
+ *                   anywhere inside v_e, so the answer is the best cell
+ *                   (|q|, v_e, j) over j >= 1 (plus j = 0 when v_e = v_s and
+ *                   the walk starts at offset 0), the smallest j on ties.
  *   orc_dp_dense_at Either form with the walk starting after the first j0
  *                   bases of v_s: the initial condition moves to
  *                   H_{0, v_s, j0} = 0 (a read seeded inside a vertex); with
@@ -166,6 +172,20 @@ static void row_answer(const ograph *g, const int32_t *h, int32_t v_s, int32_t j
     }
 }
 
+/* Global form with a free end gap in the walk: the best cell of v_e's row
+ * segment, over j >= 1 plus (v_e, 0) when v_e is the start vertex and the
+ * walk starts at offset 0 (as in row_answer, a cell (v, 0) is otherwise the
+ * copy of a predecessor's last cell, which lies outside v_e); the smallest
+ * j on ties.  out[0] = INF_H when no cell of v_e is reached. */
+static void row_answer_in(const ograph *g, const int32_t *h, int32_t v_e, int32_t v_s, int32_t j0, int32_t *out)
+{
+    out[0] = INF_H; out[1] = v_e; out[2] = (int32_t)vlen(g, v_e);
+    for (int64_t j = 0; j <= vlen(g, v_e); j++) {
+        if (j == 0 && !(v_e == v_s && j0 == 0)) continue;
+        if (h[g->base[v_e] + j] < out[0]) { out[0] = h[g->base[v_e] + j]; out[2] = (int32_t)j; }
+    }
+}
+
 /* out[0]=d*, out[1]=end vertex, out[2]=end offset j, out[3]=max sweeps in a row.
  * Returns 0, or -1 on allocation failure / non-convergence. */
 /* Called with every finished row i >= row_lo (after its fixpoint). */
@@ -228,7 +248,7 @@ static int32_t *dense_last_row(const ograph *g, const uint8_t *q, int32_t qlen, 
  * smallest row value; among rows that reach it the largest i wins (the
  * fewest unaligned bases), then the row's own end rule. */
 typedef struct {
-    int32_t v_s, j0, v_e;
+    int32_t v_s, j0, v_e, wfree;
     int32_t d, ev, ej, i;     /* best so far; d = INF_H: none */
 } clip_best;
 
@@ -236,7 +256,9 @@ static void clip_row(void *cbv, const ograph *g, int32_t i, const int32_t *h)
 {
     clip_best *cb = (clip_best *)cbv;
     int32_t o[3];
-    if (cb->v_e >= 0) {
+    if (cb->v_e >= 0 && cb->wfree) {
+        row_answer_in(g, h, cb->v_e, cb->v_s, cb->j0, o);
+    } else if (cb->v_e >= 0) {
         int32_t Le = (int32_t)vlen(g, cb->v_e);
         o[0] = h[g->base[cb->v_e] + Le]; o[1] = cb->v_e; o[2] = Le;
     } else {
@@ -265,10 +287,12 @@ int orc_dp_dense(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
 /* The same with the walk starting after the first j (j0 <= j <= j1 <=
  * |v_s|, free within the window; j1 < 0 means j1 = j0) bases of v_s and,
  * when v_e >= 0, the global form: out[0] is then H_{|q|, v_e, |v_e|} (-1
- * when unreachable), out[1] = v_e, out[2] = |v_e|. */
+ * when unreachable), out[1] = v_e, out[2] = |v_e|; with wfree, the best
+ * cell of v_e (row_answer_in) and its offset. */
 int orc_dp_dense_at(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
                     const int32_t *src, const int32_t *dst,
-                    const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t j1, int32_t v_e, int32_t *out)
+                    const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t j1, int32_t v_e, int32_t wfree,
+                    int32_t *out)
 {
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
@@ -279,6 +303,9 @@ int orc_dp_dense_at(int32_t n, const uint8_t *seq, const int64_t *off, int64_t n
     if (!last) { graph_free(&g); return -1; }
     if (v_e < 0) {
         row_answer(&g, last, v_s, j0, out);
+    } else if (wfree) {
+        row_answer_in(&g, last, v_e, v_s, j0, out);
+        if (out[0] >= INF_H) { out[0] = -1; out[2] = (int32_t)vlen(&g, v_e); }
     } else {
         int32_t h = last[g.base[v_e] + vlen(&g, v_e)];
         out[0] = h >= INF_H ? -1 : h; out[1] = v_e; out[2] = (int32_t)vlen(&g, v_e);
@@ -295,7 +322,7 @@ int orc_dp_dense_at(int32_t n, const uint8_t *seq, const int64_t *off, int64_t n
 int orc_dp_dense_clip(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
                       const int32_t *src, const int32_t *dst,
                       const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t j1, int32_t v_e,
-                      int32_t e, int32_t *out)
+                      int32_t wfree, int32_t e, int32_t *out)
 {
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
@@ -304,7 +331,7 @@ int orc_dp_dense_clip(int32_t n, const uint8_t *seq, const int64_t *off, int64_t
         graph_free(&g);
         return -1;
     }
-    clip_best cb = {v_s, j0, v_e, INF_H, -1, -1, -1};
+    clip_best cb = {v_s, j0, v_e, wfree, INF_H, -1, -1, -1};
     int maxsw = 0;
     int32_t *last = dense_rows(&g, q, qlen, v_s, j0, j1, qlen - e, clip_row, &cb, &maxsw);
     if (!last) { graph_free(&g); return -1; }
@@ -631,6 +658,8 @@ static int dq_push(dqueue *q, int32_t v, int32_t k)
  *   max_score   stop with status 1 when d exceeds it (-1: unbounded).
  *   e_free      free end gap in the query: the end test takes any row
  *               i >= |q| - e_free (0: the whole query).
+ *   wfree       global form with a free end gap in the walk: the end test
+ *               of extension mode restricted to cells of v_e.
  * out[0] = distance (-1 when stopped), out[1..2] = end (v, j), out[3] = status,
  * out[4] = query bases left unaligned.
  * work[0] = sum over scores of |F_s| (entries after extension, before
@@ -639,8 +668,8 @@ static int dq_push(dqueue *q, int32_t v, int32_t k)
  * s < counts_cap. */
 int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
             const int32_t *src, const int32_t *dst,
-            const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t j1, int32_t v_e, int32_t e_free,
-            int32_t a_diff, int32_t max_score, int32_t *out, int64_t *work, int32_t *counts, int32_t counts_cap)
+            const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t j1, int32_t v_e, int32_t wfree,
+            int32_t e_free, int32_t a_diff, int32_t max_score, int32_t *out, int64_t *work, int32_t *counts, int32_t counts_cap)
 {
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
@@ -716,7 +745,7 @@ int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
         /* ---- end test, global form (Algorithm 1 as printed): the diagonal
          * of the end cell (v_e, |q| - |v_e|) has reached offset |v_e|.  An
          * empty wavefront means v_e cannot be reached (out[3] = 2). */
-        if (v_e >= 0) {
+        if (v_e >= 0 && !wfree) {
             /* with a free end gap, the cell (i, v_e, |v_e|) of the largest
              * i >= |q| - e_free that has been reached */
             int32_t Le = (int32_t)vlen(&g, v_e), hit = -1;
@@ -727,25 +756,33 @@ int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
             if (hit >= 0) { out[0] = d; out[1] = v_e; out[2] = Le; out[4] = qlen - hit; break; }
             if (Qn.n == 0) { out[3] = 2; break; }
         }
-        /* ---- end test (extension mode): some wavefront cell has consumed
-         * the whole query. */
-        if (v_e < 0) {
-            /* the largest i >= |q| - e_free over the front cells, then the
-             * smallest (v, j) among that row's end cells */
+        /* ---- end test (extension mode, and the global form with a free
+         * end gap in the walk): some wavefront cell that can end a walk (in
+         * v_e for the latter) has consumed the whole query.  A cell (v, 0)
+         * ends a walk only at the start (v_s with offset 0): otherwise it is
+         * the copy of a predecessor's last cell. */
+        if (v_e < 0 || wfree) {
+            /* the largest i >= |q| - e_free over those front cells, then the
+             * smallest (v, j) among that row's */
             int32_t imax = -1, bv = -1, bj = -1;
             for (int64_t p = 0; p < Qn.n; p++) {
-                hent *e = hm_find(&H, dkey(Qn.v[p], Qn.k[p]));
+                int32_t v = Qn.v[p];
+                hent *e = hm_find(&H, dkey(v, Qn.k[p]));
                 int32_t i = Qn.k[p] + e->off;
+                if (v_e >= 0 && v != v_e) continue;
+                if (e->off == 0 && !(v == v_s && j0 == 0)) continue;
                 if (i >= i_lo && i > imax) imax = i;
             }
             for (int64_t p = 0; p < Qn.n && imax >= 0; p++) {
                 int32_t v = Qn.v[p], k = Qn.k[p];
                 hent *e = hm_find(&H, dkey(v, k));
                 if (k + e->off != imax) continue;
+                if (v_e >= 0 && v != v_e) continue;
                 if (e->off == 0 && !(v == v_s && j0 == 0)) continue;
                 if (bv < 0 || v < bv || (v == bv && e->off < bj)) { bv = v; bj = e->off; }
             }
             if (imax >= 0) { out[0] = d; out[1] = bv; out[2] = bj; out[4] = qlen - imax; break; }
+            if (v_e >= 0 && Qn.n == 0) { out[3] = 2; break; }
         }
 
         /* ---- Algorithm 4 (pruning) on the extended wavefront */

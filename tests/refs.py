@@ -323,6 +323,82 @@ def brute_force_global_clip(labels, edges, q: bytes, v_s: int, v_e: int, e: int,
     return best
 
 
+def brute_force_global_wfree(labels, edges, q: bytes, v_s: int, v_e: int, j0: int = 0, j1: int = None):
+    """Global form with a free end gap in the walk: every walk from v_s
+    (after its first j bases, j0 <= j <= j1) that reaches v_e, cut after any
+    j >= 1 bases of v_e (or at the cell before v_s's first base when v_e =
+    v_s and the walk starts at offset 0, as the extension form's end rule
+    has it), scored by edit distance to q.  Returns (d, set of
+    end offsets in v_e reaching d), (-1, set()) when v_e cannot be reached.
+    Walks longer than |q| + max(|q|, S) bases, S the shortest spelled length
+    that reaches the first base of v_e, cannot be optimal, which bounds the
+    enumeration on cyclic graphs."""
+    import heapq
+    if j1 is None:
+        j1 = j0
+    q = (q.decode() if isinstance(q, (bytes, bytearray)) else q).upper()
+    n = len(q)
+    succ = {}
+    for a, b in edges:
+        succ.setdefault(a, []).append(b)
+    # shortest spelled length before the first base of each vertex (start: j0)
+    dist = {}
+    pq = [(0, v_s)]
+    seen = set()
+    while pq:
+        d, v = heapq.heappop(pq)
+        if v in seen:
+            continue
+        seen.add(v)
+        dist[v] = d
+        stay = len(labels[v]) - (j0 if (v == v_s and d == 0) else 0)
+        for u in succ.get(v, []):
+            if u not in seen:
+                heapq.heappush(pq, (d + stay, u))
+    if v_e not in dist:
+        return -1, set()
+    limit = n + max(n, dist[v_e] + 1)
+    best = [1 << 60]
+    ends = set()
+    qa = list(q)
+
+    def note(d, j):
+        if d < best[0]:
+            best[0] = d
+            ends.clear()
+        if d == best[0]:
+            ends.add(j)
+
+    def step(col, c):
+        new = [col[0] + 1]
+        for i in range(1, n + 1):
+            new.append(min(col[i - 1] + (qa[i - 1] != c), col[i] + 1, new[i - 1] + 1))
+        return new
+
+    def dfs(v, col, depth, first=0):
+        lab = labels[v].upper()
+        for j in range(first, len(lab)):
+            col = step(col, lab[j])
+            depth += 1
+            if v == v_e:
+                note(col[n], j + 1)
+            # as in the extension form, the cell before v_s's first base holds
+            # this value too when the walk can step from here into v_s, and it
+            # is an end cell when the walk started there
+            if j + 1 == len(lab) and v_e == v_s and j0 == 0 and v_s in succ.get(v, []):
+                note(col[n], 0)
+            if depth > limit or min(col) > best[0]:
+                return
+        for u in succ.get(v, []):
+            dfs(u, col, depth)
+
+    for j in range(j0, j1 + 1):
+        if v_s == v_e and (j >= 1 or j0 == 0):
+            note(n, j)          # the start cell itself: nothing of the walk spelled
+        dfs(v_s, list(range(n + 1)), 0, j)
+    return best[0], ends
+
+
 def mutate(rng, s: bytes, err: float) -> bytes:
     """Substitutions, insertions and deletions, each at rate err/3 per base."""
     out = bytearray()

@@ -572,3 +572,85 @@ def test_query_end_gap_zero_is_the_plain_form_and_full_gap_is_the_longest_spelle
         d, _, _, clip = O.dp_dense_clip(g, q, v_s, len(q))
         longest = max(i for i in range(len(q) + 1) if O.dp_dense_at(g, q[:i], v_s)[0] == 0)
         assert (d, clip) == (0, len(q) - longest), case
+
+
+# ---------------------------------------------------------------------------
+# global form with a free end gap in the walk: the walk may end anywhere
+# inside v_e (one of the variants Section 2.2 points to)
+# ---------------------------------------------------------------------------
+def test_walk_end_gap_hand_cases():
+    g = (["ACGT", "TTGCA"], [(0, 1)])
+    # ACGTTTG: ends after TTG (the CA left unspelled is free)
+    assert O.dp_dense_at(g, b"ACGTTTG", 0, v_e=1, wfree=True) == (0, 1, 3)
+    assert O.gwf(g, b"ACGTTTG", 0, v_e=1, wfree=True)["end_j"] == 3
+    # the fixed end pays for the two unspelled bases
+    assert O.dp_dense_at(g, b"ACGTTTG", 0, v_e=1)[0] == 2
+    # ACGTTG: ACGTT plus an insertion, tied with ACGTTT and a mismatch; the
+    # smaller end offset wins
+    assert O.dp_dense_at(g, b"ACGTTG", 0, v_e=1, wfree=True) == (1, 1, 1)
+    # ACGT: the walk must enter v_e; one base of it costs one deletion
+    assert O.dp_dense_at(g, b"ACGT", 0, v_e=1, wfree=True) == (1, 1, 1)
+    # ending inside the start vertex: ACG is spelled by v_0 alone
+    assert O.dp_dense_at(g, b"ACG", 0, v_e=0, wfree=True) == (0, 0, 3)
+    # empty query, v_e = v_s, offset 0: the start cell itself ends the walk
+    assert O.dp_dense_at(g, b"", 0, v_e=0, wfree=True) == (0, 0, 0)
+    # with a start offset the start cell (v_s, 2) is an ordinary end cell
+    assert O.dp_dense_at(g, b"", 0, 2, v_e=0, wfree=True) == (0, 0, 2)
+    assert O.dp_dense_at(g, b"", 0, v_e=1, wfree=True) == (5, 1, 1)
+
+
+def test_walk_end_gap_brute_force_random_tiny():
+    """The dense form and Algorithms 1-3 against walk enumeration (every walk
+    to v_e cut after every base of v_e), with start offsets and windows, and
+    with a free end gap in the query against enumeration over its prefixes."""
+    rng = np.random.default_rng(991)
+    n_inside = 0
+    for case in range(300):
+        labels, edges, q, v_s = refs.random_case(rng, n_vtx=int(rng.integers(1, 5)), max_label=5,
+                                                 p_edge=0.35, qlen=int(rng.integers(0, 8)))
+        L = len(labels[v_s])
+        j0 = int(rng.integers(0, L + 1)) if rng.random() < 0.5 else 0
+        j1 = int(rng.integers(j0, L + 1)) if rng.random() < 0.3 else j0
+        v_e = int(rng.integers(0, len(labels)))
+        g = (labels, edges)
+        bd, bends = refs.brute_force_global_wfree(labels, edges, q, v_s, v_e, j0, j1)
+        d, ev, ej = O.dp_dense_at(g, q, v_s, j0, v_e, j1=j1, wfree=True)
+        if bd < 0:
+            assert d == -1, case
+            assert O.gwf(g, q, v_s, v_e=v_e, j0=j0, j1=j1, wfree=True)["status"] == 2, case
+            continue
+        assert (d, ev, ej) == (bd, v_e, min(bends)), (case, labels, edges, q, v_s, v_e, j0, j1)
+        n_inside += ej < len(labels[v_e])
+        gw = O.gwf(g, q, v_s, v_e=v_e, j0=j0, j1=j1, wfree=True)
+        assert (gw["status"], gw["dist"], gw["end_v"], gw["end_j"]) == (0, d, ev, ej), case
+        # never worse than the fixed end, which is one of its candidates
+        fixed = O.dp_dense_at(g, q, v_s, j0, v_e, j1=j1)[0]
+        assert d <= fixed, case
+        # with a free end gap in the query: the best over prefixes, ties to the longest
+        e = int(rng.integers(0, len(q) + 1))
+        want = min((refs.brute_force_global_wfree(labels, edges, q[:i], v_s, v_e, j0, j1)[0], -i)
+                   for i in range(len(q) - e, len(q) + 1))
+        dc, _, _, clip = O.dp_dense_clip(g, q, v_s, e, j0, j1, v_e, wfree=True)
+        assert (dc, -(len(q) - clip)) == want, (case, e)
+        gc = O.gwf(g, q, v_s, v_e=v_e, j0=j0, j1=j1, e=e, wfree=True)
+        assert (gc["dist"], gc["clip"]) == (dc, clip), (case, e)
+    assert n_inside > 50
+
+
+def test_walk_end_gap_on_chains_is_the_best_prefix_ending_in_the_end_vertex():
+    """On a chain the free walk end is the textbook edit distance of the
+    query against the best prefix of the spelled chain that ends inside v_e."""
+    rng = np.random.default_rng(992)
+    for case in range(80):
+        nv = int(rng.integers(1, 7))
+        labels = ["".join("ACGT"[x] for x in rng.integers(0, 4, size=int(rng.integers(1, 6)))) for _ in range(nv)]
+        edges = [(i, i + 1) for i in range(nv - 1)]
+        a = int(rng.integers(0, nv))
+        b = int(rng.integers(a, nv))
+        q = "".join("ACGT"[x] for x in rng.integers(0, 4, size=int(rng.integers(0, 14)))).encode()
+        before = len("".join(labels[a:b]))
+        t = "".join(labels[a:b + 1]).encode()
+        lo = 0 if (a == b) else before + 1
+        want = min(refs.ed(q, t[:p]) for p in range(lo, len(t) + 1))
+        assert O.dp_dense_at((labels, edges), q, a, v_e=b, wfree=True)[0] == want, case
+        assert O.gwf((labels, edges), q, a, v_e=b, wfree=True)["dist"] == want, case
