@@ -92,6 +92,14 @@ typedef struct {
                                longest; 0: the whole query is aligned, as in
                                Definition 2.2, which penalises the query's end
                                gaps (>= 0; values above |q| act as |q|)            */
+    int32_t walk_end_free;  /* global form: 1 lets the walk end anywhere inside the
+                               end vertex (a free end gap in the walk, one of the
+                               variants Section 2.2 points to): the best cell
+                               (|q|, v_e, j) over j >= 1, plus j = 0 when v_e is
+                               the start vertex and the walk starts at offset 0;
+                               the smallest j on ties.  0: the walk ends at the
+                               last base of v_e (Definition 2.2).  No effect in
+                               extension mode, whose end is already free (0/1) */
 } gwfa_opts;
 
 typedef struct {

@@ -7,7 +7,8 @@ an optional end segment for the global form.  Give one start for every query
 (--start) or one per query in a tab-separated file (--starts: query name,
 start segment, then optionally offset, window end, end segment; '.' leaves a
 field unset).  --query-end-free E lets up to E trailing query bases stay
-unaligned at no cost (a soft clip).  Output, one tab-separated line per
+unaligned at no cost (a soft clip); with end segments, --walk-end-free lets
+the walk end anywhere inside its end segment.  Output, one tab-separated line per
 query: name, length, status, distance, end segment, bases of it consumed,
 start offset, query bases clipped, walk (oriented segment names), CIGAR of
 the query against the walk's string.
@@ -76,6 +77,8 @@ def main(argv=None) -> int:
     ap.add_argument("--a-diff", type=int, default=50)
     ap.add_argument("--query-end-free", type=int, default=0,
                     help="trailing query bases that may stay unaligned at no cost")
+    ap.add_argument("--walk-end-free", action="store_true",
+                    help="with end segments: the walk may end anywhere inside its end segment")
     ap.add_argument("--cigar", action="store_true", help="also write CIGARs (base-level alignments)")
     ap.add_argument("--forward-only", action="store_true", help="one vertex per segment, + + links only")
     ap.add_argument("--out", default="-")
@@ -120,11 +123,12 @@ def main(argv=None) -> int:
         from . import train_prune
         W = train_prune.load()
         o = gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=W["tau"], mlp_gate=W["gate"], mlp_period=W["period"],
-                      query_end_free=a.query_end_free)
+                      query_end_free=a.query_end_free, walk_end_free=a.walk_end_free)
     elif a.prune == "heuristic":
-        o = gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=a.a_diff, query_end_free=a.query_end_free)
+        o = gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=a.a_diff, query_end_free=a.query_end_free,
+                      walk_end_free=a.walk_end_free)
     else:
-        o = gwfa.opts(query_end_free=a.query_end_free)
+        o = gwfa.opts(query_end_free=a.query_end_free, walk_end_free=a.walk_end_free)
 
     ctx = gwfa.Context(0)
     graph = gwfa.Graph.of(ctx, gfa.graph)

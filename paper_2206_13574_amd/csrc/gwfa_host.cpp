@@ -179,6 +179,7 @@ void gwfa_opts_default(gwfa_opts* o) {
     o->mlp_gate = 0;
     o->mlp_period = 1;
     o->query_end_free = 0;
+    o->walk_end_free = 0;
 }
 
 const char* gwfa_strerror(int code) {
@@ -363,6 +364,7 @@ static int check_opts(const gwfa_ctx* ctx, const gwfa_opts* o) {
     }
     if (o->max_score < -1) return GWFA_ERR_ARG;
     if (o->query_end_free < 0) return GWFA_ERR_ARG;
+    if (o->walk_end_free != 0 && o->walk_end_free != 1) return GWFA_ERR_ARG;
     if (o->traceback != 0 && o->traceback != 1) return GWFA_ERR_ARG;
     return GWFA_OK;
 }
@@ -397,6 +399,7 @@ static int fill_args(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     A.prune = opts->prune; A.a_diff = opts->a_diff; A.traceback = opts->traceback; A.max_score = opts->max_score;
     A.keep_threshold = opts->keep_threshold; A.mlp_gate = opts->mlp_gate; A.mlp_period = opts->mlp_period;
     A.end_free = opts->query_end_free;
+    A.walk_free = opts->walk_end_free;
     A.mlp_w = ctx->d_mlp; A.mlp_scale = ctx->d_mlp_scale;
     A.dir_factor = ctx->dir_factor;
     A.dump = d_dump; A.dump_cap = d_dump ? dump_cap : 0; A.dump_count = (unsigned long long*)d_dump_count;

@@ -36,6 +36,7 @@ struct KArgs {
     float keep_threshold;
     int32_t mlp_gate, mlp_period;
     int32_t end_free;                // free end gap in the query (trailing bases)
+    int32_t walk_free;               // global form: the walk may end anywhere inside the end vertex
     const uint16_t* mlp_w;           // bf16 weights (device) or null
     const float* mlp_scale;          // 8 feature scales (device) or null
     float* dump;                     // per-entry trace records (16 x 4 bytes) or null

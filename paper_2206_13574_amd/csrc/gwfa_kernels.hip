@@ -276,6 +276,7 @@ struct Q {
     int32_t j0, j1;   // start window: the walk starts after the first j bases of vs, j0 <= j <= j1
     int32_t ve;       // end vertex (global form) or -1 (extension mode)
     int32_t ilo;      // end rows: ilo .. qlen (qlen minus the free end gap in the query)
+    bool wfree;       // global form: the walk may end anywhere inside ve
     ull* dir;
     Page* pages;
     ull* mkey;
@@ -297,6 +298,15 @@ __device__ __forceinline__ int32_t trace_push(const Q& q, Shared& S, int32_t v, 
     return ms;
 }
 
+// Whether the front cell (v, o) of a diagonal can end a walk (the label of v
+// has Lv bases): extension mode, any cell; global form, the last cell of ve,
+// or any cell of ve when the walk's end gap is free.  A cell (v, 0) ends a
+// walk only as the start cell (vs, 0).
+__device__ __forceinline__ bool ends_walk(const Q& q, int32_t v, int32_t o, int32_t Lv) {
+    if (q.ve >= 0 && (v != q.ve || (!q.wfree && o != Lv))) return false;
+    return o >= 1 || (v == q.vs && q.j0 == 0);
+}
+
 // Records an extended diagonal: its record word when it is new or reached
 // the vertex end, the end test and the pruning reductions; returns the number
 // of out-edges to cross (0 unless the vertex end was reached).
@@ -308,15 +318,16 @@ __device__ __forceinline__ int record_entry(const Q& q, Shared& S, int32_t v, in
     // can advance it; in the global form the search goes on past i = |q|)
     if (mark || o == Lv || i == q.qlen) q.pages[d].R[k & 31] = mkR(q.gen, o);
     // end test: extension mode, any cell of the last query row; global form,
-    // the cell at the end of the end vertex (Algorithm 1).  Offset-0 cells
-    // end a walk only at the start cell (vs, 0).  With a free end gap in the
-    // query every row from ilo on ends: the largest row reached is found
-    // here, its smallest end cell once the score is complete.
-    if (i >= q.ilo && (q.ve < 0 || (v == q.ve && o == Lv))) {
+    // the cell at the end of the end vertex (Algorithm 1), or any cell of
+    // the end vertex with a free end gap in the walk.  Offset-0 cells end a
+    // walk only at the start cell (vs, 0): another one is the copy of a
+    // predecessor's last cell.  With a free end gap in the query every row
+    // from ilo on ends: the largest row reached is found here, its smallest
+    // end cell once the score is complete.
+    if (i >= q.ilo && ends_walk(q, v, o, Lv)) {
         S.found = 1;
         if (q.ilo < q.qlen) atomicMax(&S.iend, i);
-        else if (q.ve >= 0 || o >= 1 || (v == q.vs && q.j0 == 0))
-            atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
+        else atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
     }
     if (q.track) {
         atomicMax(&S.amax, i + W);
@@ -455,6 +466,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     q.j0 = __builtin_amdgcn_readfirstlane(A.v_off ? A.v_off[r] : 0);
     q.j1 = __builtin_amdgcn_readfirstlane(A.v_off_hi ? A.v_off_hi[r] : q.j0);
     q.ilo = max(0, q.qlen - A.end_free);
+    q.wfree = A.walk_free != 0;
     gwfa_result* out = A.res + r;
     const int64_t t_begin = (int64_t)wall_clock64();
     const int64_t* __restrict__ seg_off = A.seg_off;
@@ -931,8 +943,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     // the end cells of row iend (all of them are in this score's list)
                     for (int32_t idx = tid; idx < ntot; idx += BLOCK) {
                         const int32_t v = Ld.v[idx], o = Ld.o[idx];
-                        if (Ld.k[idx] + o != iend) continue;
-                        if (q.ve >= 0 ? (v == q.ve && o == Ld.l[idx]) : (o >= 1 || (v == q.vs && q.j0 == 0)))
+                        if (Ld.k[idx] + o == iend && ends_walk(q, v, o, Ld.l[idx]))
                             atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
                     }
                     __syncthreads();

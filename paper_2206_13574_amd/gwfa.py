@@ -42,7 +42,8 @@ assert RESULT_DTYPE.itemsize == 64
 class Opts(ctypes.Structure):
     _fields_ = [("prune", ctypes.c_int32), ("a_diff", ctypes.c_int32), ("keep_threshold", ctypes.c_float),
                 ("traceback", ctypes.c_int32), ("max_score", ctypes.c_int32), ("end_vertex", ctypes.c_int32),
-                ("mlp_gate", ctypes.c_int32), ("mlp_period", ctypes.c_int32), ("query_end_free", ctypes.c_int32)]
+                ("mlp_gate", ctypes.c_int32), ("mlp_period", ctypes.c_int32), ("query_end_free", ctypes.c_int32),
+                ("walk_end_free", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -131,13 +132,14 @@ def exported_symbols():
 
 def opts(prune: int = PRUNE_NONE, a_diff: int = 0, keep_threshold: float = 0.0, traceback: bool = True,
          max_score: int = -1, end_vertex: int = -1, mlp_gate: int = 0, mlp_period: int = 1,
-         query_end_free: int = 0) -> Opts:
+         query_end_free: int = 0, walk_end_free: bool = False) -> Opts:
     o = Opts()
     _lib.gwfa_opts_default(ctypes.byref(o))
     o.prune, o.a_diff, o.keep_threshold = int(prune), int(a_diff), float(keep_threshold)
     o.traceback, o.max_score, o.end_vertex = int(bool(traceback)), int(max_score), int(end_vertex)
     o.mlp_gate, o.mlp_period = int(mlp_gate), int(mlp_period)
     o.query_end_free = int(query_end_free)
+    o.walk_end_free = int(bool(walk_end_free))
     return o
 
 

@@ -110,3 +110,46 @@ def test_global_shared_end_vertex_and_errors(G):
                       v_end=np.array([1, 7], np.int32))
     assert res[0]["status"] == 0 and res[0]["dist"] == 0 and res[1]["status"] == gw.ST_BAD_INPUT
     graph.close()
+
+
+def test_global_walk_end_free_tiny_random_graphs(G):
+    """The free end gap in the walk on 2,000 tiny graphs (cycles and
+    self-loops, start offsets on half of them): distance, end and work
+    bit-exact against the dense oracle and the Algorithms 1-4 transcription;
+    unreachable end vertices reported; walks end in v_e and re-score."""
+    gw, ctx = G
+    rng = np.random.default_rng(9302)
+    cases = []
+    for _ in range(2000):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(1, 7)), max_label=5, p_edge=0.35,
+                                                qlen=int(rng.integers(0, 30)))
+        L = len(labels[vs])
+        j0 = int(rng.integers(0, L + 1)) if rng.random() < 0.5 else 0
+        cases.append((labels, edges, q, vs, int(rng.integers(0, len(labels))), j0))
+    g, base = union_graph([c[:4] for c in cases])
+    say(f"{len(cases)} tiny graphs, walk end free, one launch")
+    graph = gw.Graph.of(ctx, g)
+    try:
+        seq, off = reads_of([c[2] for c in cases])
+        res, paths = gw.align(ctx, graph, seq, off, np.array([c[3] + b for c, b in zip(cases, base)], np.int32),
+                              gw.opts(walk_end_free=True),
+                              v_end=np.array([c[4] + b for c, b in zip(cases, base)], np.int32),
+                              start_off=np.array([c[5] for c in cases], np.int32),
+                              path_cap=int(off[-1]) * 4 + 256 * len(cases))
+    finally:
+        graph.close()
+    n_inside = 0
+    for i, (labels, edges, q, vs, ve, j0) in enumerate(cases):
+        d, ev, ej = O.dp_dense_at((labels, edges), q, vs, j0, ve, wfree=True)
+        r = res[i]
+        if d < 0:
+            assert r["status"] == gw.ST_UNREACHABLE, i
+            continue
+        wf = O.gwf((labels, edges), q, vs, v_e=ve, j0=j0, wfree=True)
+        assert (r["status"], r["dist"], r["end_v"] - base[i], r["end_off"], r["work"]) == \
+            (0, d, ev, ej, wf["work"]), (i, labels, edges, q, vs, ve, j0)
+        n_inside += ej < len(labels[ve])
+        p = paths[i]
+        assert p[0] == vs + base[i] and p[-1] == ve + base[i] and O.is_walk(g, p)
+        assert O.ed_global(q, O.spell_walk(g, p, ej)[j0:]) == d
+    assert n_inside > 300

@@ -162,3 +162,53 @@ def test_medium_clip_and_windows(G, form):
         if clip:
             assert (int(w[-1]) & 15) == 4 and int(w[-1]) >> 4 == clip
     assert n_clip > N_CASES // 3
+
+
+@pytest.mark.parametrize("e", [0, 20])
+def test_medium_walk_end_free(G, e):
+    """Global form with a free end gap in the walk (opts.walk_end_free): the
+    walk may end anywhere inside v_e.  Medium graphs whose queries stop
+    part-way through their last vertex, start windows on half of them, with
+    and without a free end gap in the query: distance, end, clip and work
+    bit-exact against the dense oracle and the Algorithms 1-4 transcription,
+    walks ending in v_e re-scored, CIGARs re-scored."""
+    gw, ctx = G
+    rng = np.random.default_rng(8102 + e)
+    cs = []
+    for _ in range(N_CASES):
+        labels, edges, q, vs, vl = refs.medium_case(rng)
+        L = len(labels[vs])
+        j0 = int(rng.integers(0, L + 1)) if rng.random() < 0.5 else 0
+        j1 = int(rng.integers(j0, L + 1)) if rng.random() < 0.5 else j0
+        cs.append((labels, edges, q, vs, vl, j0, j1))
+    g, base = union_graph([c[:4] for c in cs])
+    say(f"{len(cs)} medium graphs, global form, walk end free, e = {e}, then CIGARs")
+    graph = gw.Graph.of(ctx, g)
+    try:
+        seq, off = reads_of([c[2] for c in cs])
+        n = len(cs)
+        dev = lambda x: ctx.torch.from_numpy(np.ascontiguousarray(x, np.int32)).to(ctx.tdev)
+        batch = gw.upload_reads(ctx, seq, off, np.array([c[3] + b for c, b in zip(cs, base)], np.int32))
+        out = gw.alloc_out(ctx, n, int(off[-1]) * 4 + 256 * n)
+        gw.step_dev(ctx, graph, batch, out, gw.opts(query_end_free=e, walk_end_free=True),
+                    dev([c[4] + b for c, b in zip(cs, base)]), dev([c[5] for c in cs]), dev([c[6] for c in cs]))
+        res, path, _ = gw.fetch(out, n)
+        ops, coff, clen = gw.cigar_dev(ctx, graph, batch, out)
+    finally:
+        graph.close()
+    n_inside = 0
+    for i, (labels, edges, q, vs, ve, j0, j1) in enumerate(cs):
+        ee = min(e, len(q))
+        d, ev, ej, clip = O.dp_dense_clip((labels, edges), q, vs, ee, j0, j1, ve, wfree=True)
+        wf = O.gwf((labels, edges), q, vs, v_e=ve, j0=j0, j1=j1, e=ee, wfree=True)
+        r = res[i]
+        assert (r["status"], r["dist"], r["end_v"] - base[i], r["end_off"], r["clip"], r["work"]) == \
+            (0, d, ev, ej, clip, wf["work"]), i
+        n_inside += ej < len(labels[ve])
+        so = int(r["start_off"])
+        p = path[r["path_off"]:r["path_off"] + r["path_len"]]
+        assert j0 <= so <= j1 and p[0] == vs + base[i] and p[-1] == ve + base[i] and O.is_walk(g, p)
+        T = O.spell_walk(g, p, ej)[so:]
+        assert O.ed_global(q[:len(q) - clip], T) == d
+        assert clen[i] >= 0 and refs.cigar_cost(q, T, ops[coff[i]:coff[i] + clen[i]]) == d
+    assert n_inside > N_CASES // 2
