@@ -212,3 +212,44 @@ def test_medium_walk_end_free(G, e):
         assert O.ed_global(q[:len(q) - clip], T) == d
         assert clen[i] >= 0 and refs.cigar_cost(q, T, ops[coff[i]:coff[i] + clen[i]]) == d
     assert n_inside > N_CASES // 2
+
+
+@pytest.mark.parametrize("form", ["extension", "global"])
+def test_medium_learned_prune(gpu_lib, cases, form):
+    """The trained keep/drop network on the medium graphs, both forms: every
+    query finishes (or its end vertex is reported unreachable when pruning
+    emptied the wavefront), the distance is never below the exact one, the
+    traced walk is a witness between the two, and the network with every
+    diagonal kept (threshold -inf, no gate) reproduces the exact run."""
+    from paper_2206_13574_amd import train_prune
+    gw = gpu_lib
+    cs, g, base = cases
+    W = train_prune.load()
+    ctx = gw.Context(0)
+    try:
+        ctx.mlp_load(W["w_bf16"], W["scale"])
+        say(f"{form}: {len(cs)} medium graphs, learned pruning")
+        res, path, _ = _run(gw, ctx, g, base, cs, gw.opts(prune=gw.PRUNE_LEARNED, keep_threshold=W["tau"],
+                                                          mlp_gate=W["gate"], mlp_period=W["period"]), form)
+        keep_all, _, _ = _run(gw, ctx, g, base, cs, gw.opts(prune=gw.PRUNE_LEARNED, keep_threshold=-1e30,
+                                                            mlp_gate=0, mlp_period=1), form)
+    finally:
+        ctx.close()
+    over = 0
+    for i, (labels, edges, q, vs, vl) in enumerate(cs):
+        ve = vl if form == "global" else -1
+        d, ev, ej = O.dp_dense_at((labels, edges), q, vs, 0, ve)
+        wf = O.gwf((labels, edges), q, vs, v_e=ve)
+        assert (keep_all[i]["status"], keep_all[i]["dist"], keep_all[i]["end_v"] - base[i],
+                keep_all[i]["end_off"], keep_all[i]["work"]) == (0, d, ev, ej, wf["work"]), (form, i)
+        r = res[i]
+        if r["status"] == gw.ST_UNREACHABLE:
+            assert form == "global", i
+            over += 1
+            continue
+        assert r["status"] == 0 and r["dist"] >= d, (form, i)
+        over += r["dist"] > d
+        p = path[r["path_off"]:r["path_off"] + r["path_len"]]
+        e = O.ed_global(q, O.spell_walk(g, p, int(r["end_off"])))
+        assert d <= e <= r["dist"], (form, i)
+    say(f"{form}: {over} of {len(cs)} queries above the exact distance")
