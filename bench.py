@@ -254,15 +254,22 @@ def main():
     if args.prune == 0 and not args.no_compare:
         # the metric's comparison: learned pruning (and Algorithm 4) on the same
         # resident batch, outside the timed steps, against the exact distances
-        from paper_2206_13574_amd import train_prune
+        from paper_2206_13574_amd import calibrate_prune, train_prune
         W = train_prune.load()
         ctx.mlp_load(W["w_bf16"], W["scale"])
+        # the keep threshold calibrated on held-out sets of this workload's
+        # shape when there is one, else the training-shape threshold
+        shaped = calibrate_prune.load().get(args.workload)
+        tau = float(shaped["tau"]) if shaped else W["tau"]
+        tau_src = (f"held-out {args.workload}-shaped sets ({shaped['reads']} reads, graph seeds "
+                   f"{shaped['graph_seeds']})" if shaped else "held-out training-shaped sets")
         line["compare"] = {
             "learned-prune": compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
-                                          gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=W["tau"],
+                                          gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=tau,
                                                     mlp_gate=W["gate"], mlp_period=W["period"],
                                                     traceback=bool(o.traceback)),
-                                          dict(tau=W["tau"], gate=W["gate"], period=W["period"])),
+                                          dict(tau=tau, tau_calibrated_on=tau_src, gate=W["gate"],
+                                               period=W["period"])),
             "heuristic-prune": compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
                                             gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=50,
                                                       traceback=bool(o.traceback)), dict(a_diff=50)),

@@ -373,7 +373,12 @@ def cfg2(n_reads: int = 20000):
     """1 Mb backbone, SNP every ~1 kb, indel (1-50) every ~5 kb, structural
     bubble (1-10 kb arms) every ~100 kb; reads lognormal(median 10 kb,
     sigma 0.5) clipped to [1, 50] kb, per-read error U(0.1%, 5%)."""
-    g = bubble_graph(201, 1_000_000, snp_gap=1000, indel_gap=5000, indel_arm=(1, 50),
+    return cfg2_shaped(201, 202, n_reads)
+
+
+def cfg2_shaped(graph_seed: int, read_seed: int, n_reads: int):
+    """A graph and reads of cfg2's shape from other seeds (held-out sets)."""
+    g = bubble_graph(graph_seed, 1_000_000, snp_gap=1000, indel_gap=5000, indel_arm=(1, 50),
                      sv_gap=100_000, sv_arm=(1000, 10000))
 
     def length(rng, n):
@@ -382,7 +387,7 @@ def cfg2(n_reads: int = 20000):
     def err(rng, n):
         return rng.uniform(0.001, 0.05, size=n)
 
-    r = sample_reads(g, 202, n_reads, length, err)
+    r = sample_reads(g, read_seed, n_reads, length, err)
     return g, r
 
 

@@ -163,13 +163,23 @@ def test_clip_cfg1_reads_with_adapter_tails(G):
 
 
 def test_clip_negative_is_an_argument_error(G):
+    """A negative query end gap, and a walk end flag other than 0 or 1, are
+    argument errors; a query end gap above |q| acts as |q|."""
     gw, ctx = G
     g = synth.Graph.from_labels(["ACGT"], [])
     graph = gw.Graph.of(ctx, g)
+    seq, off = np.frombuffer(b"ACG", np.uint8), np.array([0, 3], np.int64)
     try:
         with pytest.raises(gw.GwfaError) as ei:
-            gw.align(ctx, graph, np.frombuffer(b"ACG", np.uint8), np.array([0, 3], np.int64),
-                     np.zeros(1, np.int32), gw.opts(query_end_free=-1))
+            gw.align(ctx, graph, seq, off, np.zeros(1, np.int32), gw.opts(query_end_free=-1))
         assert ei.value.code == gw.ERR_ARG
+        o = gw.opts()
+        o.walk_end_free = 2
+        with pytest.raises(gw.GwfaError) as ei:
+            gw.align(ctx, graph, seq, off, np.zeros(1, np.int32), o)
+        assert ei.value.code == gw.ERR_ARG
+        a, _ = gw.align(ctx, graph, np.frombuffer(b"TTT", np.uint8), off, np.zeros(1, np.int32),
+                        gw.opts(query_end_free=1000))
+        assert (a[0]["status"], a[0]["dist"], a[0]["clip"]) == (0, 0, 3)
     finally:
         graph.close()
