@@ -448,12 +448,14 @@ __device__ __forceinline__ void entry_features(float* f, int32_t s, int32_t i, i
     f[7] = log1pf((float)(qlen - i));
 }
 
-// MODE 0: exact; 1: walk lengths tracked (Algorithm 4); 2: learned keep/drop
-// or trace dump.  Each mode is its own instantiation so that the registers of
-// what it does not use are not allocated.
+// MODE 0: exact; 1: walk lengths tracked (Algorithm 4); 2: trace dump (and
+// the learned keep/drop); 3: learned keep/drop without the dump.  Each mode
+// is its own instantiation so that the registers of what it does not use
+// are not allocated.
 template <int BLOCK, int MODE>
 __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shared& S) {
-    constexpr bool LEARN = MODE == 2;
+    constexpr bool LEARN = MODE >= 2;
+    constexpr bool DUMP = MODE == 2;
     const int tid = threadIdx.x;
     Q q;
     q.rd = A.rd;
@@ -1027,7 +1029,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             if (tid == 0) { const ull t2 = wall_clock64(); S.tick[2] += t2 - tk; tk = t2; }
             n_cur = ntot;
             // ========== pruning (Algorithm 4) ==========
-            if (MODE >= 1 && A.prune == GWFA_PRUNE_HEURISTIC && amax > A.a_diff) {
+            if ((MODE == 1 || MODE == 2) && A.prune == GWFA_PRUNE_HEURISTIC && amax > A.a_diff) {
                 const Lists Ls = LL(cur);
                 const Lists Lp = LL(1 - cur);
                 VMerge vmv;
@@ -1061,7 +1063,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             }
             // ========== trace dump and learned keep/drop ==========
             const bool run_mlp = LEARN && A.prune == GWFA_PRUNE_LEARNED && n_cur >= A.mlp_gate && (s % A.mlp_period) == 0;
-            if (LEARN && (A.dump || run_mlp)) {
+            if (LEARN && ((DUMP && A.dump) || run_mlp)) {
                 const Lists Ls = LL(cur);
                 const Lists Lp = LL(1 - cur);
                 VMerge vmv;
@@ -1081,7 +1083,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         i = k + o;
                         const int32_t Lv = (int32_t)(seg_off[v + 1] - seg_off[v]);
                         entry_features(f, s, i, W, o, Lv, out_off[v + 1] - out_off[v], amax, imax, q.qlen);
-                        rec = A.dump ? 1 : 0;
+                        rec = (DUMP && A.dump) ? 1 : 0;
                         keep = 1;
                         if (run_mlp) {
                             ++evals;
@@ -1093,7 +1095,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             }
                         }
                     }
-                    if (A.dump) {
+                    if (DUMP && A.dump) {
                         // one global atomic per wave
                         int tot;
                         const int ex = wave_excl_scan(rec, tot);
@@ -1194,7 +1196,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
 // a 512-lane workgroup fills a CU alone: it takes the whole register file instead of spilling
 template <int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK, MODE == 2 ? 2 : (BLOCK >= 512 ? 1 : 3)) void k_align(KArgs A) {
-    constexpr bool LEARN = MODE == 2;
+    constexpr bool LEARN = MODE >= 2;
     __shared__ Shared S;
     char* arena = A.arena + (int64_t)blockIdx.x * A.arena_stride;
     if (LEARN && A.prune == GWFA_PRUNE_LEARNED) {
@@ -1274,11 +1276,13 @@ __global__ void k_reset(int32_t* queue, ull* path_cursor, int32_t* retry_count, 
 // launch helpers (called from the host code)
 // ---------------------------------------------------------------------------
 hipError_t gwfa_launch_align(const KArgs& A, int lanes, int groups, hipStream_t st) {
-    // the learned keep/drop and the trace dump live in their own instantiation
-    const int mode = (A.prune == GWFA_PRUNE_LEARNED || A.dump != nullptr) ? 2 : (A.prune != GWFA_PRUNE_NONE ? 1 : 0);
+    // the trace dump and the learned keep/drop live in their own instantiations
+    const int mode = A.dump != nullptr ? 2
+                     : (A.prune == GWFA_PRUNE_LEARNED ? 3 : (A.prune != GWFA_PRUNE_NONE ? 1 : 0));
     (void)hipGetLastError();   // the launch status below must not report an older, unrelated error
 #define GWFA_LAUNCH(L)                                                                                     \
-    if (mode == 2) hipLaunchKernelGGL((gwfa_dev::k_align<L, 2>), dim3(groups), dim3(L), 0, st, A);        \
+    if (mode == 3) hipLaunchKernelGGL((gwfa_dev::k_align<L, 3>), dim3(groups), dim3(L), 0, st, A);        \
+    else if (mode == 2) hipLaunchKernelGGL((gwfa_dev::k_align<L, 2>), dim3(groups), dim3(L), 0, st, A);   \
     else if (mode == 1) hipLaunchKernelGGL((gwfa_dev::k_align<L, 1>), dim3(groups), dim3(L), 0, st, A);   \
     else hipLaunchKernelGGL((gwfa_dev::k_align<L, 0>), dim3(groups), dim3(L), 0, st, A);
     switch (lanes) {
