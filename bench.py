@@ -263,18 +263,22 @@ def main():
         tau = float(shaped["tau"]) if shaped else W["tau"]
         tau_src = (f"held-out {args.workload}-shaped sets ({shaped['reads']} reads, graph seeds "
                    f"{shaped['graph_seeds']})" if shaped else "held-out training-shaped sets")
-        line["compare"] = {
-            "learned-prune": compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
-                                          gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=tau,
-                                                    mlp_gate=W["gate"], mlp_period=W["period"],
-                                                    traceback=bool(o.traceback)),
-                                          dict(tau=tau, tau_calibrated_on=tau_src, gate=W["gate"],
-                                               period=W["period"])),
-            "heuristic-prune": compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
-                                            gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=50,
-                                                      traceback=bool(o.traceback)), dict(a_diff=50)),
-            "exact_align_ms": align_avg_s * 1000.0,
-        }
+        # each mode at its own measured lanes per query (pruned wavefronts are
+        # small: narrower workgroups keep more queries in flight)
+        lanes_l = tune.best_lanes(args.workload, "learned")
+        lanes_h = tune.best_lanes(args.workload, "heuristic")
+        ctx.config(**dict(cfg, lanes=lanes_l))
+        learned = compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
+                               gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=tau, mlp_gate=W["gate"],
+                                         mlp_period=W["period"], traceback=bool(o.traceback)),
+                               dict(tau=tau, tau_calibrated_on=tau_src, gate=W["gate"], period=W["period"],
+                                    lanes=lanes_l))
+        ctx.config(**dict(cfg, lanes=lanes_h))
+        heuristic = compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
+                                 gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=50, traceback=bool(o.traceback)),
+                                 dict(a_diff=50, lanes=lanes_h))
+        line["compare"] = {"learned-prune": learned, "heuristic-prune": heuristic,
+                           "exact_align_ms": align_avg_s * 1000.0, "exact_lanes": cfg["lanes"]}
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(g, r, seconds=args.cpu_seconds)

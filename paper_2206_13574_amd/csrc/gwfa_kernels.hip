@@ -52,8 +52,10 @@ constexpr int PAGE = 32;
 constexpr int32_t CLAIM_BASE = 0x40000000;   // record value while a crossing round claims it
 constexpr int F_GROW = 1;   // directory / trace capacity exceeded: restart with a bigger one
 constexpr int F_LIST = 2;   // list / candidate capacity exceeded: re-run on a larger tier
-constexpr int XS_LDS = 1024;   // crossing entries sorted in LDS up to this many
-constexpr int NB_LDS = 512 + 4;   // staged batch of the expansion (largest block + halo)
+// Crossing entries sorted in LDS (virtual merge) up to this many per
+// workgroup of `block` lanes; larger sets are sorted in the arena.
+constexpr int xs_lds(int block) { return block >= 256 ? 1024 : 4 * block; }
+
 
 struct Page {
     ull R[PAGE];    // (gen << 32) | record offset (or CLAIM_BASE + round)
@@ -236,7 +238,12 @@ struct Lists {
     int64_t* b;
 };
 
+// Workgroup LDS, sized for the workgroup (merge keys, the staged batch) and
+// the mode (the network's weights only where it runs).
+template <int BLOCK, int MODE>
 struct Shared {
+    static constexpr int XS = xs_lds(BLOCK);
+    static constexpr int NB = BLOCK + 4;
     int32_t read;
     int32_t n_out;    // entries in the list being built (outputs, then crossing entries)
     int32_t ncand;
@@ -257,14 +264,14 @@ struct Shared {
     ull mlp;
     ull tick[4];      // wall-clock ticks per phase (thread 0)
     int32_t scan[16];
-    ull skeys[XS_LDS];
-    int32_t sidx[XS_LDS];
-    int32_t xcnt[XS_LDS];   // merge: main-list entries below each crossing entry
+    ull skeys[XS];
+    int32_t sidx[XS];
+    int32_t xcnt[XS];       // merge: main-list entries below each crossing entry
     ull skeys2[64];         // crossing keys sorted by rank counting (small sets)
     // expansion: the entries of one batch of the source list at slots 2 ..
     // BLOCK+1 plus two neighbours on each side (slots 0, 1, BLOCK+2, BLOCK+3)
-    int32_t nbv[NB_LDS], nbk[NB_LDS], nbo[NB_LDS], nbd[NB_LDS], nbw[NB_LDS], nbt[NB_LDS];
-    uint16_t mlpw[4808];    // pruning network (bfloat16), loaded once per launch
+    int32_t nbv[NB], nbk[NB], nbo[NB], nbd[NB], nbw[NB], nbt[NB];
+    uint16_t mlpw[MODE >= 2 ? 4808 : 2];   // pruning network (bfloat16), loaded once per launch
     float mscale[8];        // feature scales
 };
 
@@ -289,7 +296,8 @@ struct Q {
 
 // Algorithm 5: T gets (v, t) unless the pair is already there; the index of
 // the pair's slot in the de-duplication map is its trace index.
-__device__ __forceinline__ int32_t trace_push(const Q& q, Shared& S, int32_t v, int32_t tprev) {
+template <class SH>
+__device__ __forceinline__ int32_t trace_push(const Q& q, SH& S, int32_t v, int32_t tprev) {
     const int ms = dir_insert(q.mkey, q.mask, dkey(v, tprev), &S.mn);
     if (ms < 0) { atomicOr(&S.flags, F_GROW); return -1; }
     // the slot's (v, tprev) is fixed by its key, so every inserter may write it
@@ -310,7 +318,8 @@ __device__ __forceinline__ bool ends_walk(const Q& q, int32_t v, int32_t o, int3
 // Records an extended diagonal: its record word when it is new or reached
 // the vertex end, the end test and the pruning reductions; returns the number
 // of out-edges to cross (0 unless the vertex end was reached).
-__device__ __forceinline__ int record_entry(const Q& q, Shared& S, int32_t v, int32_t k, int32_t o, int32_t W,
+template <class SH>
+__device__ __forceinline__ int record_entry(const Q& q, SH& S, int32_t v, int32_t k, int32_t o, int32_t W,
                                             int32_t d, bool mark, int32_t Lv, int32_t deg) {
     const int32_t i = k + o;
     // the record is written when the diagonal is new or may leave the
@@ -337,7 +346,8 @@ __device__ __forceinline__ int record_entry(const Q& q, Shared& S, int32_t v, in
 }
 
 // Extends one admitted diagonal (Algorithm 2) and records it.
-__device__ __forceinline__ int extend_entry(const KArgs& A, const Q& q, Shared& S, int32_t v, int32_t k,
+template <class SH>
+__device__ __forceinline__ int extend_entry(const KArgs& A, const Q& q, SH& S, int32_t v, int32_t k,
                                             int32_t& o, int32_t& W, int32_t d, bool mark, int64_t sb,
                                             int32_t Lv, int32_t deg, uint32_t& chunks) {
     const int32_t i = k + o;
@@ -453,7 +463,7 @@ __device__ __forceinline__ void entry_features(float* f, int32_t s, int32_t i, i
 // is its own instantiation so that the registers of what it does not use
 // are not allocated.
 template <int BLOCK, int MODE>
-__device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shared& S) {
+__device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shared<BLOCK, MODE>& S) {
     constexpr bool LEARN = MODE >= 2;
     constexpr bool DUMP = MODE == 2;
     const int tid = threadIdx.x;
@@ -968,7 +978,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             if (ntot == 0) { status = q.ve >= 0 ? GWFA_ST_UNREACHABLE : GWFA_ST_MAX_SCORE; break; }
             if (q.ve < 0 && s > q.qlen + 1) { status = GWFA_ST_MAX_SCORE; break; }
             // ========== merge the crossing diagonals into the sorted list ==========
-            // Small sets (<= XS_LDS) are merged virtually: their keys are sorted
+            // Small sets (<= Shared::XS) are merged virtually: their keys are sorted
             // in LDS and each gets its merged position (its rank among the
             // crossing keys plus the number of expansion outputs below it);
             // the next pass reads the list through that table.  Larger sets
@@ -977,7 +987,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             vmx = 0;
             if (m > 0) {
                 if (m > A.sort_cap) { rflags = F_LIST; break; }
-                if (m <= XS_LDS) {
+                if (m <= Shared<BLOCK, MODE>::XS) {
                     if (m <= 64) {
                         for (int i = tid; i < m; i += BLOCK) S.skeys[i] = skey(Ld.v[n1 + i], Ld.k[n1 + i]);
                         __syncthreads();
@@ -1193,16 +1203,20 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     __syncthreads();
 }
 
-// a 512-lane workgroup fills a CU alone: it takes the whole register file instead of spilling
+// Waves per SIMD the compiler must allow: 3 (168 registers), 2 for the dump
+// instantiation; a 512-lane workgroup fills a CU alone: it takes the whole
+// register file instead of spilling.
 template <int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK, MODE == 2 ? 2 : (BLOCK >= 512 ? 1 : 3)) void k_align(KArgs A) {
     constexpr bool LEARN = MODE >= 2;
-    __shared__ Shared S;
+    __shared__ Shared<BLOCK, MODE> S;
     char* arena = A.arena + (int64_t)blockIdx.x * A.arena_stride;
-    if (LEARN && A.prune == GWFA_PRUNE_LEARNED) {
-        for (int i = threadIdx.x; i < MLP_N; i += BLOCK) S.mlpw[i] = A.mlp_w[i];
-        if (threadIdx.x < 8) S.mscale[threadIdx.x] = A.mlp_scale[threadIdx.x];
-        __syncthreads();
+    if constexpr (LEARN) {
+        if (A.prune == GWFA_PRUNE_LEARNED) {
+            for (int i = threadIdx.x; i < MLP_N; i += BLOCK) S.mlpw[i] = A.mlp_w[i];
+            if (threadIdx.x < 8) S.mscale[threadIdx.x] = A.mlp_scale[threadIdx.x];
+            __syncthreads();
+        }
     }
     for (;;) {
         if (threadIdx.x == 0) S.read = atomicAdd(A.queue, 1);
@@ -1275,24 +1289,35 @@ __global__ void k_reset(int32_t* queue, ull* path_cursor, int32_t* retry_count, 
 // ---------------------------------------------------------------------------
 // launch helpers (called from the host code)
 // ---------------------------------------------------------------------------
+namespace {
+template <int L>
+void launch_modes(const KArgs& A, int mode, int groups, hipStream_t st) {
+    if constexpr (L >= 128) {
+        if (mode == 3) { hipLaunchKernelGGL((gwfa_dev::k_align<L, 3>), dim3(groups), dim3(L), 0, st, A); return; }
+        if (mode == 2) { hipLaunchKernelGGL((gwfa_dev::k_align<L, 2>), dim3(groups), dim3(L), 0, st, A); return; }
+    } else {
+        // the network's instantiations need at least 128 lanes (at 64 the
+        // compiler cannot fit them in 3 waves per SIMD): those queries run
+        // on 128-lane workgroups, one per arena as always
+        if (mode >= 2) { launch_modes<128>(A, mode, groups, st); return; }
+    }
+    if (mode == 1) hipLaunchKernelGGL((gwfa_dev::k_align<L, 1>), dim3(groups), dim3(L), 0, st, A);
+    else hipLaunchKernelGGL((gwfa_dev::k_align<L, 0>), dim3(groups), dim3(L), 0, st, A);
+}
+}  // namespace
+
 hipError_t gwfa_launch_align(const KArgs& A, int lanes, int groups, hipStream_t st) {
     // the trace dump and the learned keep/drop live in their own instantiations
     const int mode = A.dump != nullptr ? 2
                      : (A.prune == GWFA_PRUNE_LEARNED ? 3 : (A.prune != GWFA_PRUNE_NONE ? 1 : 0));
     (void)hipGetLastError();   // the launch status below must not report an older, unrelated error
-#define GWFA_LAUNCH(L)                                                                                     \
-    if (mode == 3) hipLaunchKernelGGL((gwfa_dev::k_align<L, 3>), dim3(groups), dim3(L), 0, st, A);        \
-    else if (mode == 2) hipLaunchKernelGGL((gwfa_dev::k_align<L, 2>), dim3(groups), dim3(L), 0, st, A);   \
-    else if (mode == 1) hipLaunchKernelGGL((gwfa_dev::k_align<L, 1>), dim3(groups), dim3(L), 0, st, A);   \
-    else hipLaunchKernelGGL((gwfa_dev::k_align<L, 0>), dim3(groups), dim3(L), 0, st, A);
     switch (lanes) {
-    case 64: GWFA_LAUNCH(64) break;
-    case 128: GWFA_LAUNCH(128) break;
-    case 256: GWFA_LAUNCH(256) break;
-    case 512: GWFA_LAUNCH(512) break;
+    case 64: launch_modes<64>(A, mode, groups, st); break;
+    case 128: launch_modes<128>(A, mode, groups, st); break;
+    case 256: launch_modes<256>(A, mode, groups, st); break;
+    case 512: launch_modes<512>(A, mode, groups, st); break;
     default: return hipErrorInvalidValue;
     }
-#undef GWFA_LAUNCH
     return hipGetLastError();
 }
 

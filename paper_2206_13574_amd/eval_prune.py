@@ -72,6 +72,10 @@ def main(argv=None):
     ap.add_argument("--period", type=int, default=None)
     ap.add_argument("--repeats", type=int, default=1)
     ap.add_argument("--lanes", type=int, default=None, help="lanes per query (default: the tuned configuration)")
+    ap.add_argument("--lanes-heuristic", type=int, default=None,
+                    help="lanes per query of the Algorithm 4 runs (default: the measured ones, else --lanes)")
+    ap.add_argument("--lanes-learned", type=int, default=None,
+                    help="lanes per query of the network runs (default: the measured ones, else --lanes)")
     ap.add_argument("--json", default=None, help="also write the rows to this file")
     ap.add_argument("--no-baselines", action="store_true",
                     help="skip the untrained and keep-all networks (each about as slow as exact or slower)")
@@ -102,19 +106,28 @@ def main(argv=None):
     gate = W["gate"] if a.gate is None else a.gate
     period = W["period"] if a.period is None else a.period
     rows = []
+    cur = {"lanes": cfg["lanes"]}
 
     def run(mode, o, note=""):
         ctx.stats(reset=True)
         ms, res = timed(ctx, graph, batch, out, o, a.repeats)
         st = ctx.stats(reset=True)
-        rows.append(dict(mode=mode, note=note, ms=ms, res=res, mlp=st["mlp_evals"] / a.repeats,
+        rows.append(dict(mode=mode, note=note, ms=ms, res=res, lanes=cur["lanes"], mlp=st["mlp_evals"] / a.repeats,
                          pruned=st["pruned"] / a.repeats))
         log(f"{mode:28s} {ms:10.1f} ms  {note}")
         return res
 
     exact = run("exact", gwfa.opts(traceback=False))
+    lanes_h = a.lanes_heuristic or (a.lanes if a.lanes else tune.best_lanes(a.workload, "heuristic"))
+    lanes_l = a.lanes_learned or (a.lanes if a.lanes else tune.best_lanes(a.workload, "learned"))
+    ctx.config(**dict(cfg, lanes=lanes_h))
+    cur["lanes"] = lanes_h
+    log(f"Algorithm 4 runs at {lanes_h} lanes per query")
     for ad in [int(x) for x in a.a_diffs.split(",") if x]:
         run(f"heuristic a_diff={ad}", gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=ad, traceback=False))
+    ctx.config(**dict(cfg, lanes=lanes_l))
+    cur["lanes"] = lanes_l
+    log(f"network runs at {lanes_l} lanes per query")
     ctx.mlp_load(W["w_bf16"], W["scale"])
     taus = ([W["tau"] + d for d in (-4.0, -2.0, -1.0, 0.0, 1.0, 2.0, 4.0)] if a.taus == "auto"
             else [float(x) for x in a.taus.split(",")])
@@ -142,10 +155,10 @@ def main(argv=None):
                    workload=a.workload, gate=gate, period=period)
         table.append(row)
         print(json.dumps(row), flush=True)
-    print("\n| mode | ms | bases/s | speedup | reads over | mean excess | excess (over) | work/exact | MLP evals |")
-    print("|---|---|---|---|---|---|---|---|---|")
+    print("\n| mode | lanes | ms | bases/s | speedup | reads over | mean excess | excess (over) | work/exact | MLP evals |")
+    print("|---|---|---|---|---|---|---|---|---|---|")
     for t in table:
-        print(f"| {t['mode']} {t['note']} | {t['ms']:.1f} | {t['bases_per_s']:.3e} | {t['speedup']:.2f} | "
+        print(f"| {t['mode']} {t['note']} | {t['lanes']} | {t['ms']:.1f} | {t['bases_per_s']:.3e} | {t['speedup']:.2f} | "
               f"{t['frac_over']:.4f} | {t['mean_excess']:.3f} | {t['mean_excess_over']:.2f} | "
               f"{t['work_vs_exact']:.3f} | {t['mlp']:.3g} |")
     if a.json:

@@ -46,6 +46,15 @@ def best_config(workload: str) -> dict:
     return out
 
 
+def best_lanes(workload: str, mode: str) -> int:
+    """Lanes per query for a pruning mode ("heuristic" or "learned"): pruned
+    wavefronts are small, so these modes may prefer narrower workgroups than
+    the exact configuration; the exact configuration's lanes when none was
+    measured."""
+    c = _load().get(f"{_device_name()}|{workload}") or {}
+    return int(c.get(f"lanes_{mode}", best_config(workload)["lanes"]))
+
+
 def _time_config(g, sub, cfg, repeats, stream):
     from . import gwfa
     import torch
