@@ -221,6 +221,23 @@ def main():
     achieved = alg_bytes / align_avg_s / 1e9
     traffic, traffic_src = recorded_traffic(args.workload, cfg["lanes"])
     pack_avg_s = float(np.mean(pack_ms)) / 1000.0
+    # context for the pack's rate: a plain device copy that moves the same
+    # number of bytes (half read, half written), timed the same way
+    copy_gbs = None
+    with torch.cuda.stream(stream):
+        half = int(bases * 1.25) // 2
+        src_t = torch.empty(half, dtype=torch.uint8, device=dev)
+        dst_t = torch.empty(half, dtype=torch.uint8, device=dev)
+        cms = []
+        for _ in range(4):
+            c0, c1 = ev(), ev()
+            c0.record(stream)
+            dst_t.copy_(src_t)
+            c1.record(stream)
+            torch.cuda.synchronize()
+            cms.append(c0.elapsed_time(c1))
+        copy_gbs = 2 * half / (float(np.median(cms[1:])) / 1000.0) / 1e9
+        del src_t, dst_t
     pack_bytes = bases * 1.25
     line = {
         "metric": "query bases aligned/s on 1 GPU; exact vs learned-prune at <=1% reads over ED",
@@ -247,7 +264,9 @@ def main():
                      "entries_per_launch": entries, "chunks_per_launch": chunks,
                      "crossings_per_launch": cross},
         "pack": {"avg_ms": pack_avg_s * 1000.0, "GB/s": pack_bytes / pack_avg_s / 1e9,
-                 "frac": pack_bytes / pack_avg_s / 1e9 / HBM_PEAK_GBS},
+                 "frac": pack_bytes / pack_avg_s / 1e9 / HBM_PEAK_GBS,
+                 "same_traffic_copy_GB/s": copy_gbs,
+                 "frac_of_copy": pack_bytes / pack_avg_s / 1e9 / copy_gbs if copy_gbs else None},
         "reruns": st["reruns"] / steps,
         "not_ok": bad,
     }
