@@ -136,6 +136,43 @@ def test_lanes_and_capacity_do_not_change_results(G):
             assert st["reruns"] > 0      # the small tier overflowed and re-ran
 
 
+def test_pruned_modes_at_every_lane_width(gpu_lib):
+    """Algorithm 4 and the trained network give the same bytes (distance,
+    end, work) at 64, 128, 256 and 512 lanes per query (the network at 64
+    lanes runs on 128-lane workgroups), and Algorithm 4 equals its CPU
+    transcription."""
+    from paper_2206_13574_amd import train_prune
+    gw = gpu_lib
+    g = synth.bubble_graph(79, 6000, snp_gap=60, indel_gap=300, indel_arm=(1, 20))
+    r = synth.sample_reads(g, 80, 96, lambda rng, n: rng.integers(200, 3000, size=n),
+                           lambda rng, n: rng.uniform(0.0, 0.08, size=n))
+    qs = [r.read(i) for i in range(r.n)]
+    W = train_prune.load()
+    modes = {"heuristic": gw.opts(prune=gw.PRUNE_HEURISTIC, a_diff=30),
+             "learned": gw.opts(prune=gw.PRUNE_LEARNED, keep_threshold=W["tau"], mlp_gate=W["gate"],
+                                mlp_period=W["period"])}
+    ref = {}
+    for lanes in (256, 64, 128, 512):
+        say(f"pruned modes at {lanes} lanes")
+        c2 = gw.Context(0)
+        try:
+            c2.config(lanes=lanes)
+            c2.mlp_load(W["w_bf16"], W["scale"])
+            for name, o in modes.items():
+                res, _ = run(gw, c2, g, qs, r.v_start, o)
+                assert (res["status"] == 0).all(), (name, lanes)
+                key = np.stack([res["dist"], res["end_v"], res["end_off"], res["work"].astype(np.int32)])
+                if name not in ref:
+                    ref[name] = key
+                else:
+                    assert (key == ref[name]).all(), (name, lanes)
+        finally:
+            c2.close()
+    for i in range(r.n):
+        w = O.gwf(g, qs[i], int(r.v_start[i]), a_diff=30)
+        assert tuple(int(x) for x in ref["heuristic"][:, i]) == (w["dist"], w["end_v"], w["end_j"], w["work"]), i
+
+
 @pytest.mark.parametrize("a_diff", [8, 30, 120, 400])
 def test_heuristic_prune_matches_algorithm_4(G, a_diff):
     gw, ctx = G
