@@ -31,9 +31,14 @@ def _load():
 
 
 def _device_name():
+    """Cache key of the device: its ISA and compute-unit count (the marketing
+    name depends on which lookup tables the process found)."""
     try:
         import torch
-        return torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+        if not torch.cuda.is_available():
+            return "cpu"
+        p = torch.cuda.get_device_properties(0)
+        return f"{p.gcnArchName.split(':')[0]}x{p.multi_processor_count}"
     except Exception:
         return "cpu"
 
