@@ -5,9 +5,12 @@ growth of the first working-memory tier.
 `autotune` times the whole batch step for each candidate on a stratified
 sample of the queries (every k-th query of the length-sorted batch, so long
 and short queries are both represented), searching one parameter at a time,
-and keeps the fastest; the result is cached per (device name, workload) in
-tune_cache.json beside this file, which `best_config` reads.
-Usage: python -m paper_2206_13574_amd.tune --workload cfg2
+and keeps the fastest; the result is cached per (device, workload) in
+tune_cache.json beside this file, which `best_config` reads.  With --mode
+heuristic or learned it times that pruning mode (Algorithm 4 at a_diff 50,
+or the trained network) at every lanes-per-query width on the workload's
+exact configuration and caches the fastest as lanes_<mode> (`best_lanes`).
+Usage: python -m paper_2206_13574_amd.tune --workload cfg2 [--mode learned]
 """
 from __future__ import annotations
 
@@ -60,22 +63,38 @@ def best_lanes(workload: str, mode: str) -> int:
     return int(c.get(f"lanes_{mode}", best_config(workload)["lanes"]))
 
 
-def _time_config(g, sub, cfg, repeats, stream):
+def _mode_opts(mode: str):
+    """Options and network weights (or None) of a mode."""
+    from . import gwfa
+    if mode == "exact":
+        return gwfa.opts(), None
+    if mode == "heuristic":
+        return gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=50), None
+    from . import train_prune
+    W = train_prune.load()
+    return gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=W["tau"], mlp_gate=W["gate"],
+                     mlp_period=W["period"]), W
+
+
+def _time_config(g, sub, cfg, repeats, stream, mode: str = "exact"):
     from . import gwfa
     import torch
+    o, W = _mode_opts(mode)
     ctx = gwfa.Context(0, stream=stream)
     try:
         ctx.config(**cfg)
+        if W is not None:
+            ctx.mlp_load(W["w_bf16"], W["scale"])
         graph = gwfa.Graph.of(ctx, g)
         with torch.cuda.stream(stream):
             batch = gwfa.upload_reads(ctx, sub.seq, sub.off, sub.v_start)
             out = gwfa.alloc_out(ctx, sub.n, int(sub.off[-1]) // 4 + 64 * sub.n)
-        gwfa.step_dev(ctx, graph, batch, out, gwfa.opts())     # warm-up (allocates the arenas)
+        gwfa.step_dev(ctx, graph, batch, out, o)     # warm-up (allocates the arenas)
         torch.cuda.synchronize()
         ctx.stats(reset=True)
         t0 = time.perf_counter()
         for _ in range(repeats):
-            gwfa.step_dev(ctx, graph, batch, out, gwfa.opts())
+            gwfa.step_dev(ctx, graph, batch, out, o)
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / repeats
         reruns = ctx.stats()["reruns"]
@@ -132,7 +151,31 @@ def autotune(workload: str, g, r, sample: int = 0, repeats: int = 2, save: bool 
     log(f"[tune] best {best}: {best_t * 1000:.1f} ms")
     if save:
         c = _load()
-        c[f"{_device_name()}|{workload}"] = dict(best, ms=best_t * 1000.0, sample=sub.n)
+        key = f"{_device_name()}|{workload}"
+        c[key] = dict(c.get(key, {}), **best, ms=best_t * 1000.0, sample=sub.n)
+        with open(_CACHE, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+    return best
+
+
+def tune_mode_lanes(workload: str, g, r, mode: str, repeats: int = 2, save: bool = True, log=print) -> int:
+    """Lanes per query for a pruning mode on the whole batch, the other
+    parameters at the workload's exact configuration."""
+    import torch
+    stream = torch.cuda.Stream()
+    base = best_config(workload)
+    times = {}
+    # the network's instantiations start at 128 lanes (64 runs the same kernel)
+    for lanes in ((128, 256, 512) if mode == "learned" else (64, 128, 256, 512)):
+        t, reruns = _time_config(g, r, dict(base, lanes=lanes), repeats, stream, mode)
+        times[lanes] = t
+        log(f"[tune] {mode} lanes={lanes}: {t * 1000:.1f} ms (re-runs {reruns})")
+    best = min(times, key=times.get)
+    log(f"[tune] {mode}: best lanes {best}")
+    if save:
+        c = _load()
+        key = f"{_device_name()}|{workload}"
+        c[key] = dict(c.get(key, {}), **{f"lanes_{mode}": best, f"ms_{mode}": times[best] * 1000.0})
         with open(_CACHE, "w") as f:
             json.dump(c, f, indent=1, sort_keys=True)
     return best
@@ -145,9 +188,14 @@ def main(argv=None):
     ap.add_argument("--workload", default="cfg2", choices=("cfg1", "cfg2", "cfg3", "cfg4", "cfg4b"))
     ap.add_argument("--sample", type=int, default=0, help="queries to time (0: all)")
     ap.add_argument("--repeats", type=int, default=2)
+    ap.add_argument("--mode", default="exact", choices=("exact", "heuristic", "learned"),
+                    help="exact: the full search; a pruning mode: its lanes per query only")
     a = ap.parse_args(argv)
     g, r = synth.cfg4(sparse=True) if a.workload == "cfg4b" else getattr(synth, a.workload)()
-    autotune(a.workload, g, r, sample=a.sample, repeats=a.repeats, log=lambda m: print(m, flush=True))
+    if a.mode == "exact":
+        autotune(a.workload, g, r, sample=a.sample, repeats=a.repeats, log=lambda m: print(m, flush=True))
+    else:
+        tune_mode_lanes(a.workload, g, r, a.mode, repeats=a.repeats, log=lambda m: print(m, flush=True))
 
 
 if __name__ == "__main__":
