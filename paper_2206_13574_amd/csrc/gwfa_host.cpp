@@ -148,10 +148,12 @@ void set_tiers(gwfa_ctx* ctx, int32_t dir_log2_max, int32_t list_cap) {
     int per_cu = gwfa_align_blocks_per_cu(ctx->lanes);
     if (per_cu <= 0) per_cu = 4;
     const int groups = ctx->groups > 0 ? ctx->groups : ctx->n_cu * per_cu;
+    // the old arenas go first, so that the free memory the new tiers are
+    // sized from includes them
+    for (int i = 0; i < N_TIERS; ++i) free_tier(ctx->tier[i]);
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b == 0) free_b = (size_t)64 << 30;
     for (int i = 0; i < N_TIERS; ++i) {
-        free_tier(ctx->tier[i]);
         Tier& t = ctx->tier[i];
         t.dir_log2_max = std::min(dir_log2_max + 2 * i, 24);
         t.list_cap = (int32_t)std::min<int64_t>((int64_t)list_cap << (2 * i), (int64_t)1 << 26);
