@@ -139,9 +139,7 @@ int gwfa_ctx_create(int device, void *hip_stream, gwfa_ctx **out);
 void gwfa_ctx_destroy(gwfa_ctx *ctx);
 
 /* Working-memory / launch configuration (used by the autotuner).
- *   lanes_per_query: 64, 128, 256 or 512 threads cooperate on one query
- *             (the learned pruning and the trace dump need at least 128: at
- *             64 they run 128-lane workgroups, one per persistent slot);
+ *   lanes_per_query: 64, 128, 256 or 512 threads cooperate on one query;
  *   n_groups: persistent workgroups (0 = as many as can be resident on the
  *             device at once for the chosen lanes_per_query);
  *   dir_log2_max: log2 of the largest per-query diagonal-page directory

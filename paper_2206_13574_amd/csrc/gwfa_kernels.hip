@@ -1292,15 +1292,8 @@ __global__ void k_reset(int32_t* queue, ull* path_cursor, int32_t* retry_count, 
 namespace {
 template <int L>
 void launch_modes(const KArgs& A, int mode, int groups, hipStream_t st) {
-    if constexpr (L >= 128) {
-        if (mode == 3) { hipLaunchKernelGGL((gwfa_dev::k_align<L, 3>), dim3(groups), dim3(L), 0, st, A); return; }
-        if (mode == 2) { hipLaunchKernelGGL((gwfa_dev::k_align<L, 2>), dim3(groups), dim3(L), 0, st, A); return; }
-    } else {
-        // the network's instantiations need at least 128 lanes (at 64 the
-        // compiler cannot fit them in 3 waves per SIMD): those queries run
-        // on 128-lane workgroups, one per arena as always
-        if (mode >= 2) { launch_modes<128>(A, mode, groups, st); return; }
-    }
+    if (mode == 3) { hipLaunchKernelGGL((gwfa_dev::k_align<L, 3>), dim3(groups), dim3(L), 0, st, A); return; }
+    if (mode == 2) { hipLaunchKernelGGL((gwfa_dev::k_align<L, 2>), dim3(groups), dim3(L), 0, st, A); return; }
     if (mode == 1) hipLaunchKernelGGL((gwfa_dev::k_align<L, 1>), dim3(groups), dim3(L), 0, st, A);
     else hipLaunchKernelGGL((gwfa_dev::k_align<L, 0>), dim3(groups), dim3(L), 0, st, A);
 }

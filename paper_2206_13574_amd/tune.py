@@ -165,8 +165,7 @@ def tune_mode_lanes(workload: str, g, r, mode: str, repeats: int = 2, save: bool
     stream = torch.cuda.Stream()
     base = best_config(workload)
     times = {}
-    # the network's instantiations start at 128 lanes (64 runs the same kernel)
-    for lanes in ((128, 256, 512) if mode == "learned" else (64, 128, 256, 512)):
+    for lanes in (64, 128, 256, 512):
         t, reruns = _time_config(g, r, dict(base, lanes=lanes), repeats, stream, mode)
         times[lanes] = t
         log(f"[tune] {mode} lanes={lanes}: {t * 1000:.1f} ms (re-runs {reruns})")

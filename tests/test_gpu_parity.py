@@ -138,9 +138,8 @@ def test_lanes_and_capacity_do_not_change_results(G):
 
 def test_pruned_modes_at_every_lane_width(gpu_lib):
     """Algorithm 4 and the trained network give the same bytes (distance,
-    end, work) at 64, 128, 256 and 512 lanes per query (the network at 64
-    lanes runs on 128-lane workgroups), and Algorithm 4 equals its CPU
-    transcription."""
+    end, work) at 64, 128, 256 and 512 lanes per query, and Algorithm 4
+    equals its CPU transcription."""
     from paper_2206_13574_amd import train_prune
     gw = gpu_lib
     g = synth.bubble_graph(79, 6000, snp_gap=60, indel_gap=300, indel_arm=(1, 20))
