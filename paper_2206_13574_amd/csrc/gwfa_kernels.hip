@@ -1097,7 +1097,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         keep = 1;
                         if (run_mlp) {
                             ++evals;
-                            const float z = mlp_logit(f, S.mscale, S.mlpw);
+                            const float z = BLOCK == 64 ? mlp_logit_call(f, S.mscale, S.mlpw)
+                                                        : mlp_logit(f, S.mscale, S.mlpw);
                             keep = (z >= A.keep_threshold || i + W == amax) ? 1 : 0;   // the furthest diagonal stays
                             if (!keep) {
                                 q.pages[Ls.d[ph]].R[k & 31] = mkR(q.gen, o);   // record kept, as in Algorithm 4

@@ -27,10 +27,7 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
 
 // logit of one entry: x = bf16(f * scale); the order of every sum is the
 // order of the loops below
-// Not inlined: as a call of its own its registers do not add to those of the
-// alignment loop around it (inlined, a 64-lane instantiation of the learned
-// mode spills hundreds of registers).  The arithmetic is the same.
-__device__ __attribute__((noinline)) float mlp_logit(const float* f, const float* scale, const uint16_t* w) {
+__device__ __forceinline__ float mlp_logit(const float* f, const float* scale, const uint16_t* w) {
     float x[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) x[i] = round_bf16(f[i] * scale[i]);
@@ -61,6 +58,14 @@ __device__ __attribute__((noinline)) float mlp_logit(const float* f, const float
         z = fmaf(bf2f(w[MW_W3 + j]), round_bf16(fmaxf(acc, 0.0f)), z);
     }
     return z;
+}
+
+// The same as a call of its own: its registers then do not add to those of
+// the alignment loop around it (inlined into a 64-lane workgroup's loop the
+// compiler spills hundreds of registers); where inlining fits, the call's
+// overhead is not worth paying.
+__device__ __attribute__((noinline)) float mlp_logit_call(const float* f, const float* scale, const uint16_t* w) {
+    return mlp_logit(f, scale, w);
 }
 
 }  // namespace gwfa_nn
