@@ -59,7 +59,8 @@ def _load():
     lib.orc_ed_global.restype = i64
     lib.orc_ed_banded.argtypes = [P, i64, P, i64, i64]
     lib.orc_ed_banded.restype = i64
-    lib.orc_gwf.argtypes = [i32, P, P, i64, P, P, P, i32, i32, i32, i32, i32, i32, i32, i32, i32, P, P, P, i32]
+    lib.orc_gwf.argtypes = [i32, P, P, i64, P, P, P, i32, i32, i32, i32, i32, i32, i32, i32, i32, P, P, P, i32,
+                            P, i64, P]
     lib.orc_dp_dense_clip.argtypes = [i32, P, P, i64, P, P, P, i32, i32, i32, i32, i32, i32, i32, P]
     lib.orc_dp_dense_clip.restype = ctypes.c_int
     lib.orc_gwf.restype = ctypes.c_int
@@ -231,28 +232,36 @@ def ed_banded(a, b, D: int) -> int:
 
 
 def gwf(g, q, v_s: int, a_diff: int = 0, max_score: int = -1, counts_cap: int = 0, v_e: int = -1, j0: int = 0,
-        j1: int = -1, e: int = 0, wfree: bool = False):
+        j1: int = -1, e: int = 0, wfree: bool = False, entries_cap: int = 0):
     """Algorithms 1-4 in extension mode (v_e = -1) or in the global form with
     end vertex v_e (wfree: ending anywhere inside v_e); the walk starts after the first j bases of v_s, j free in
     j0..j1 (j1 = -1: j = j0); up to e trailing query bases may stay unaligned
     (`clip` in the result: how many did).  Returns a dict with dist, end_v, end_j, status (0 ok,
     1 max_score, 2 end vertex unreachable), work (sum |F_s|), diagonals,
-    crossings and optionally the per-score |F_s| list."""
+    crossings and optionally the per-score |F_s| list; with entries_cap > 0
+    also "entries", an (m, 5) int32 array of (score, v, k, offset, W~) for
+    every entry of every extended wavefront (at most entries_cap rows)."""
     lib = _load()
     G = OGraph.of(g)
     qq = _u8(q)
     out = np.zeros(5, dtype=np.int32)
     work = np.zeros(3, dtype=np.int64)
     counts = np.zeros(max(counts_cap, 1), dtype=np.int32)
+    ent = np.zeros((max(entries_cap, 1), 5), dtype=np.int32)
+    ent_n = np.zeros(1, dtype=np.int64)
     rc = lib.orc_gwf(*G._args(), _ptr(qq), len(qq), int(v_s), int(j0), int(j1), int(v_e), int(bool(wfree)), int(e),
                      int(a_diff), int(max_score),
-                     _ptr(out), _ptr(work), _ptr(counts) if counts_cap else None, int(counts_cap))
+                     _ptr(out), _ptr(work), _ptr(counts) if counts_cap else None, int(counts_cap),
+                     _ptr(ent) if entries_cap else None, int(entries_cap), _ptr(ent_n) if entries_cap else None)
     if rc != 0:
         raise RuntimeError("orc_gwf failed")
     res = dict(dist=int(out[0]), end_v=int(out[1]), end_j=int(out[2]), status=int(out[3]), clip=int(out[4]),
                work=int(work[0]), diagonals=int(work[1]), crossings=int(work[2]))
     if counts_cap:
         res["counts"] = counts[: min(counts_cap, max(res["dist"], 0) + 1)].tolist()
+    if entries_cap:
+        res["entries"] = ent[: min(int(ent_n[0]), entries_cap)].copy()
+        res["entries_total"] = int(ent_n[0])
     return res
 
 

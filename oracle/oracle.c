@@ -665,11 +665,14 @@ static int dq_push(dqueue *q, int32_t v, int32_t k)
  * work[0] = sum over scores of |F_s| (entries after extension, before
  * pruning); work[1] = number of diagonals ever created (size of H~);
  * work[2] = crossings admitted.  counts (optional) receives |F_s| for
- * s < counts_cap. */
+ * s < counts_cap.  ent (optional) receives five words per entry of every
+ * extended wavefront, score by score: (d, v, k, offset, W~), at most
+ * ent_cap entries; *ent_n gets the number there were. */
 int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
             const int32_t *src, const int32_t *dst,
             const uint8_t *q, int32_t qlen, int32_t v_s, int32_t j0, int32_t j1, int32_t v_e, int32_t wfree,
-            int32_t e_free, int32_t a_diff, int32_t max_score, int32_t *out, int64_t *work, int32_t *counts, int32_t counts_cap)
+            int32_t e_free, int32_t a_diff, int32_t max_score, int32_t *out, int64_t *work, int32_t *counts, int32_t counts_cap,
+            int32_t *ent, int64_t ent_cap, int64_t *ent_n)
 {
     ograph g;
     if (graph_init(&g, n, seq, off, ne, src, dst, 0)) { graph_free(&g); return -1; }
@@ -685,6 +688,7 @@ int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
     int rc = 0;
     out[0] = -1; out[1] = -1; out[2] = -1; out[3] = 0; out[4] = 0;
     work[0] = work[1] = work[2] = 0;
+    if (ent_n) *ent_n = 0;
     if (hm_grow(&H)) { rc = -1; goto done; }
 
     /* Algorithm 1: H~_{v_s,0} <- 0; Q <- [(v_s,0)]; d <- 0.  A walk that
@@ -741,6 +745,16 @@ int orc_gwf(int32_t n, const uint8_t *seq, const int64_t *off, int64_t ne,
         for (int64_t p = 0; p < Qn.n; p++) hm_find(&H, dkey(Qn.v[p], Qn.k[p]))->round = 0;
         work[0] += Qn.n;
         if (counts && d < counts_cap) counts[d] = (int32_t)Qn.n;
+        if (ent && ent_n) {
+            for (int64_t p = 0; p < Qn.n; p++) {
+                if (*ent_n < ent_cap) {
+                    const hent *e = hm_find(&H, dkey(Qn.v[p], Qn.k[p]));
+                    int32_t *w = ent + 5 * *ent_n;
+                    w[0] = d; w[1] = Qn.v[p]; w[2] = Qn.k[p]; w[3] = e->off; w[4] = e->W;
+                }
+                (*ent_n)++;
+            }
+        }
 
         /* ---- end test, global form (Algorithm 1 as printed): the diagonal
          * of the end cell (v_e, |q| - |v_e|) has reached offset |v_e|.  An

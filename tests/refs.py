@@ -441,3 +441,116 @@ def medium_case(rng):
     vs = int(rng.integers(0, n // 2))
     t, walk = spell_random_walk(rng, labels, edges, vs, int(rng.integers(50, 3000)))
     return labels, edges, mutate(rng, t, float(rng.uniform(0.0, 0.12))), vs, walk[-1]
+
+
+# ---------------------------------------------------------------------------
+# An independent pairwise wavefront with the pruning rule of Algorithm 4, for
+# graphs whose every walk from the start has the same length up to each base
+# (chains; SNP bubbles of two one-base alleles).  There the aligned walk
+# length W~ of a front cell is its position in the walk, so Algorithm 4's
+# quantity a = i + W~ is the textbook a = i + j of a pairwise alignment and
+# the graph transcription must give the same distance and end position.
+# ---------------------------------------------------------------------------
+def pairwise_wf_pruned(q: bytes, cols, a_diff: int = 0):
+    """Extension-form alignment of q against a prefix of the column string
+    `cols` (cols[j] = the set of bases allowed at position j), by furthest-
+    reaching diagonals d = j - i (i query bases, j columns consumed).  Per
+    score: extend every diagonal by its exact-match run; stop when some
+    diagonal has consumed q (end = the smallest such j); if the largest
+    a = i + j exceeds a_diff, keep only diagonals with a_max - a < a_diff
+    (a dropped diagonal keeps its furthest point as its record); then expand
+    by insertion (i+1), deletion (j+1) and mismatch (both), per diagonal the
+    furthest candidate, admitted only past the diagonal's record.
+    Returns (distance, end j)."""
+    q = q.upper()
+    n, m = len(q), len(cols)
+    rec = {}
+    wf = {0: 0}
+    s = 0
+    while True:
+        for dg in list(wf):
+            i = wf[dg]
+            while i < n and i + dg < m and q[i] in cols[i + dg]:
+                i += 1
+            wf[dg] = i
+            rec[dg] = i
+        ends = [i + dg for dg, i in wf.items() if i == n]
+        if ends:
+            return s, min(ends)
+        if a_diff > 0:
+            amax = max(2 * i + dg for dg, i in wf.items())
+            if amax > a_diff:
+                wf = {dg: i for dg, i in wf.items() if amax - (2 * i + dg) < a_diff}
+        nxt = {}
+        for dg, i in wf.items():
+            j = i + dg
+            cand = []
+            if i < n:
+                cand.append((dg - 1, i + 1))          # query base alone
+            if j < m:
+                cand.append((dg + 1, i))              # column alone
+            if i < n and j < m:
+                cand.append((dg, i + 1))              # substitution
+            for nd, ni in cand:
+                if nd in rec and rec[nd] >= ni:
+                    continue
+                if ni > nxt.get(nd, -1):
+                    nxt[nd] = ni
+        wf = nxt
+        s += 1
+
+
+def chain_case(rng, length: int, max_piece: int):
+    """A random string cut at random points into a chain of vertices.
+    Returns (labels, edges, column sets, backbone position of each vertex)."""
+    t = "".join("ACGT"[x] for x in rng.integers(0, 4, size=length))
+    labels, pos, p = [], [], 0
+    while p < length:
+        c = int(rng.integers(1, max_piece + 1))
+        labels.append(t[p:p + c])
+        pos.append(p)
+        p += c
+    edges = [(a, a + 1) for a in range(len(labels) - 1)]
+    return labels, edges, [frozenset(ch.encode()) for ch in t], pos
+
+
+def snp_bubble_case(rng, length: int, snp_rate: float, max_piece: int):
+    """A backbone with SNP bubbles (two one-base alleles with different
+    bases) cut into vertices in topological order.  Returns (labels, edges,
+    column sets, backbone position of each vertex, backbone string)."""
+    labels, pos, edges, cols = [], [], [], []
+    tails = []
+    p = 0
+    while p < length:
+        if p > 0 and rng.random() < snp_rate:
+            a = "ACGT"[int(rng.integers(0, 4))]
+            b = "ACGT"[("ACGT".index(a) + int(rng.integers(1, 4))) % 4]
+            ids = []
+            for x in (a, b):
+                labels.append(x)
+                pos.append(p)
+                ids.append(len(labels) - 1)
+                edges += [(t, ids[-1]) for t in tails]
+            tails = ids
+            cols.append(frozenset((a + b).encode()))
+            p += 1
+        else:
+            c = int(min(rng.integers(1, max_piece + 1), length - p))
+            s = "".join("ACGT"[x] for x in rng.integers(0, 4, size=c))
+            labels.append(s)
+            pos.append(p)
+            v = len(labels) - 1
+            edges += [(t, v) for t in tails]
+            tails = [v]
+            cols += [frozenset(ch.encode()) for ch in s]
+            p += c
+    return labels, edges, cols, pos
+
+
+def spell_cols(rng, cols) -> bytes:
+    """One string through the column sets (a random allowed base each)."""
+    out = bytearray()
+    for c in cols:
+        c = sorted(c)
+        out.append(c[int(rng.integers(0, len(c)))])
+    return bytes(out)

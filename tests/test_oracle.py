@@ -654,3 +654,120 @@ def test_walk_end_gap_on_chains_is_the_best_prefix_ending_in_the_end_vertex():
         want = min(refs.ed(q, t[:p]) for p in range(lo, len(t) + 1))
         assert O.dp_dense_at((labels, edges), q, a, v_e=b, wfree=True)[0] == want, case
         assert O.gwf((labels, edges), q, a, v_e=b, wfree=True)["dist"] == want, case
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 4 and the walk length W~ (reading R12), pinned on graphs where
+# every walk from the start has the same length up to each base: chains and
+# SNP bubbles.  There W~ of a front cell is its walk position, and the
+# graph transcription with pruning must agree with an independent pairwise
+# wavefront that applies the same keep rule to a = i + j.
+# ---------------------------------------------------------------------------
+def test_pairwise_pruned_reference_is_pinned():
+    """The pairwise reference itself: without pruning it is the textbook
+    extension-form edit distance (best over prefixes of the text, ending
+    position the shortest such prefix); with pruning never below it."""
+    rng = np.random.default_rng(4101)
+    for _ in range(300):
+        t = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, size=int(rng.integers(1, 60)))].tobytes()
+        q = refs.mutate(rng, t[:int(rng.integers(0, len(t) + 1))], float(rng.uniform(0, 0.3)))
+        cols = [frozenset([c]) for c in t]
+        row = refs.semiglobal_ed_row(q, t)
+        d, j = refs.pairwise_wf_pruned(q, cols)
+        assert d == int(row.min()) and j == int(np.argmin(row)), (q, t)
+        for a in (2, 5, 11):
+            assert refs.pairwise_wf_pruned(q, cols, a)[0] >= d
+
+
+def _walk_pos(pos, v, j):
+    return pos[v] + j
+
+
+@pytest.mark.parametrize("kind", ["chain", "snp"])
+def test_algorithm4_matches_pairwise_pruning(kind):
+    """Distance and end position of orc_gwf with Algorithm 4 equal the
+    pairwise wavefront with the same keep rule, at several a_diff, on
+    queries with errors; every extended entry's W~ is its walk position."""
+    rng = np.random.default_rng(4102 if kind == "chain" else 4103)
+    n_pruned_differs = 0
+    for case in range(250):
+        length = int(rng.integers(20, 300))
+        if kind == "chain":
+            labels, edges, cols, pos = refs.chain_case(rng, length, int(rng.integers(1, 25)))
+        else:
+            labels, edges, cols, pos = refs.snp_bubble_case(rng, length, float(rng.uniform(0.05, 0.3)),
+                                                            int(rng.integers(1, 12)))
+        t = refs.spell_cols(rng, cols)
+        q = refs.mutate(rng, t[:int(rng.integers(0, length + 1))], float(rng.uniform(0.0, 0.3)))
+        exact = None
+        for a_diff in (0, 1, 2, 3, 4, 6, 10, 17, 30, 80):
+            ref = refs.pairwise_wf_pruned(q, cols, a_diff)
+            got = O.gwf((labels, edges), q, 0, a_diff=a_diff, entries_cap=1 << 16)
+            assert got["status"] == 0
+            assert (got["dist"], _walk_pos(pos, got["end_v"], got["end_j"])) == ref, (case, a_diff, labels, q)
+            if a_diff == 0:
+                exact = got["dist"]
+                assert exact == O.dp_dense((labels, edges), q, 0)[0]
+            elif got["dist"] > exact:
+                n_pruned_differs += 1
+            ent = got["entries"]
+            assert got["entries_total"] == len(ent) == got["work"]
+            # W~ (reading R12) is the walk position of the front cell
+            assert (ent[:, 4] == np.asarray(pos)[ent[:, 1]] + ent[:, 3]).all(), (case, a_diff)
+    # the keep rule decided something: pruning changed some distances
+    assert n_pruned_differs > 100
+
+
+def test_walk_length_with_a_start_offset_on_chains():
+    """With the walk starting after j0 bases of v_s, W~ counts walk bases
+    from there: W~ = position - j0 on every entry of every score."""
+    rng = np.random.default_rng(4104)
+    for _ in range(150):
+        labels, edges, cols, pos = refs.chain_case(rng, int(rng.integers(10, 200)), int(rng.integers(2, 30)))
+        j0 = int(rng.integers(0, len(labels[0]) + 1))
+        t = refs.spell_cols(rng, cols)[j0:]
+        q = refs.mutate(rng, t[:int(rng.integers(0, len(t) + 1))], float(rng.uniform(0.0, 0.2)))
+        for a_diff in (0, 5, 20):
+            got = O.gwf((labels, edges), q, 0, a_diff=a_diff, j0=j0, entries_cap=1 << 16)
+            ref = refs.pairwise_wf_pruned(q, cols[j0:], a_diff)
+            assert (got["dist"], _walk_pos(pos, got["end_v"], got["end_j"]) - j0) == ref
+            ent = got["entries"]
+            assert (ent[:, 4] == np.asarray(pos)[ent[:, 1]] + ent[:, 3] - j0).all()
+
+
+# ---------------------------------------------------------------------------
+# The value-capped oracle is the reference of every full-size comparison, so
+# it is pinned against the dense oracle on many graphs: 10,000 tiny random
+# graphs (cycles, self-loops) and medium graphs with queries up to 3 kb.
+# ---------------------------------------------------------------------------
+def test_capped_equals_dense_10k_tiny_graphs():
+    rng = np.random.default_rng(4201)
+    n_cut = 0
+    for _ in range(10000):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(1, 9)), max_label=6,
+                                                p_edge=float(rng.uniform(0.1, 0.5)), qlen=int(rng.integers(0, 40)))
+        d, ev, ej, _ = O.dp_dense((labels, edges), q, vs)
+        D = d + int(rng.integers(0, 4))
+        assert O.dp_capped((labels, edges), q, vs, D) == (d, ev, ej), (labels, edges, q, vs, D)
+        if d > 0:
+            assert O.dp_capped((labels, edges), q, vs, d - 1)[0] == -1
+            n_cut += 1
+    assert n_cut > 8000
+
+
+def test_capped_equals_dense_medium_graphs():
+    """Medium graphs (20-200 vertices, labels up to 400 bases, bubbles, back
+    edges, self-loops) with queries of 50-3,000 bases at 0-12% error:
+    capped at the exact distance, and at a few values above it, the capped
+    oracle gives the dense oracle's distance and end."""
+    rng = np.random.default_rng(4202)
+    big = 0
+    for _ in range(200):
+        labels, edges, q, vs, _ = refs.medium_case(rng)
+        d, ev, ej, _ = O.dp_dense((labels, edges), q, vs)
+        for D in (d, d + 7, 2 * d + 1):
+            assert O.dp_capped((labels, edges), q, vs, D) == (d, ev, ej), (D, d)
+        if d > 0:
+            assert O.dp_capped((labels, edges), q, vs, d - 1)[0] == -1
+        big += d >= 100
+    assert big >= 30
