@@ -204,7 +204,9 @@ int gwfa_align(gwfa_ctx *ctx, const gwfa_graph *g, const uint8_t *q, int32_t qle
  *              longest first balances the load best);
  *   d_res      n_reads gwfa_result; d_path_buf path_cap int32 (may be NULL);
  *   d_path_used  device int64: receives the ids the walks need.
- * Start vertices are checked on the device (status GWFA_ST_BAD_INPUT).
+ * Per-query parameters are checked on the device by a screen pass before
+ * the alignment kernel: a query whose start vertex is out of range gets its
+ * result there (status GWFA_ST_BAD_INPUT) and never enters the alignment.
  * Runs on `hip_stream` (NULL = context stream).  When some query overflows its
  * working memory the library synchronises the stream and re-runs those
  * queries with larger memory before returning; otherwise the call is
@@ -330,14 +332,16 @@ void gwfa_gfa_free(gwfa_gfa *g);
 /* ---- captured launches ---------------------------------------------------
  * A plan records the alignment of one device-resident batch (the arguments
  * of gwfa_align_batch_dev, fixed at creation) as a HIP graph: the reset of
- * the work queue and counters and the first-tier launch of the persistent
- * alignment kernel, kernels only.  gwfa_plan_launch replays it on
+ * the work queue and counters, the screen pass of the query parameters and
+ * the first-tier launch of the persistent alignment kernel, kernels only.  gwfa_plan_launch replays it on
  * `hip_stream` (NULL = context stream), asynchronously, with no host work.
  * gwfa_plan_finish then synchronises that stream and re-runs, eagerly, the
  * queries that overflowed the first tier's working memory (usually none);
  * after it returns, results are complete exactly as after
  * gwfa_align_batch_dev.  The buffers named at creation must stay allocated;
- * gwfa_ctx_config invalidates the plan (its calls then return GWFA_ERR_ARG);
+ * gwfa_ctx_config invalidates the plan (its calls then return GWFA_ERR_ARG),
+ * and so does a later call on the context with more queries than any before
+ * (it moves the context's per-query lists);
  * destroy plans before their context.  Replays of one plan, like calls on one
  * context, must not overlap in time. */
 typedef struct gwfa_plan gwfa_plan;

@@ -70,6 +70,8 @@ struct gwfa_ctx {
     int32_t* d_retry_count = nullptr;
     unsigned long long* d_stats = nullptr;
     int32_t* d_retry[2] = {nullptr, nullptr};
+    int32_t* d_valid = nullptr;        // queries that passed the screen pass, in work-queue order
+    int32_t* d_valid_n = nullptr;
     int64_t retry_cap = 0;
     int64_t rerun_total = 0;
     uint16_t* d_mlp = nullptr;
@@ -221,6 +223,7 @@ int gwfa_ctx_create(int device, void* hip_stream, gwfa_ctx** out) {
     bool ok = hipMalloc((void**)&c->d_queue, sizeof(int32_t)) == hipSuccess &&
               hipMalloc((void**)&c->d_cursor, sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc((void**)&c->d_retry_count, sizeof(int32_t)) == hipSuccess &&
+              hipMalloc((void**)&c->d_valid_n, sizeof(int32_t)) == hipSuccess &&
               hipMalloc((void**)&c->d_stats, 16 * sizeof(unsigned long long)) == hipSuccess;
     if (ok) ok = hipMemset(c->d_stats, 0, 16 * sizeof(unsigned long long)) == hipSuccess &&
                  hipDeviceSynchronize() == hipSuccess;
@@ -240,6 +243,8 @@ void gwfa_ctx_destroy(gwfa_ctx* c) {
     if (c->d_retry_count) (void)hipFree(c->d_retry_count);
     if (c->d_stats) (void)hipFree(c->d_stats);
     for (auto p : c->d_retry) if (p) (void)hipFree(p);
+    if (c->d_valid) (void)hipFree(c->d_valid);
+    if (c->d_valid_n) (void)hipFree(c->d_valid_n);
     if (c->d_mlp) (void)hipFree(c->d_mlp);
     if (c->d_mlp_scale) (void)hipFree(c->d_mlp_scale);
     if (c->d_mlp_scr) (void)hipFree(c->d_mlp_scr);
@@ -385,10 +390,14 @@ static int fill_args(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     if (n_reads > 0 && (!d_packed || !d_read_off || !d_v_start || !d_res)) return GWFA_ERR_ARG;
     if (ctx->retry_cap < n_reads) {
         for (auto& p : ctx->d_retry) { if (p) (void)hipFree(p); p = nullptr; }
+        if (ctx->d_valid) (void)hipFree(ctx->d_valid);
+        ctx->d_valid = nullptr;
         ctx->retry_cap = 0;
         for (auto& p : ctx->d_retry)
             if (hipMalloc((void**)&p, (size_t)n_reads * 4) != hipSuccess) return GWFA_ERR_NOMEM;
+        if (hipMalloc((void**)&ctx->d_valid, (size_t)n_reads * 4) != hipSuccess) return GWFA_ERR_NOMEM;
         ctx->retry_cap = n_reads;
+        ctx->epoch++;   // captured plans hold the old lists
     }
     memset(&A, 0, sizeof(A));
     A.seg = g->d_seg; A.seg_off = g->d_seg_off; A.out_off = g->d_out_off; A.out_dst = g->d_out_dst; A.n_vtx = g->n_vtx;
@@ -409,11 +418,12 @@ static int fill_args(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
 }
 
 // Working memory of tier ti into A; returns the workgroups to launch.
-static int set_tier(gwfa_ctx* ctx, KArgs& A, int ti, const int32_t* order, int32_t n, int* groups) {
+static int set_tier(gwfa_ctx* ctx, KArgs& A, int ti, const int32_t* order, int32_t n, const int32_t* n_valid,
+                    int* groups) {
     int rc = ensure_tier(ctx, ti);
     if (rc) return rc;
     const Tier& t = ctx->tier[ti];
-    A.order = order; A.n_reads = n; A.tier = ti;
+    A.order = order; A.n_reads = n; A.n_valid = n_valid; A.tier = ti;
     A.retry = (ti + 1 < N_TIERS) ? ctx->d_retry[ti & 1] : nullptr;
     A.arena = t.arena; A.arena_stride = t.stride;
     A.dir_log2_max = t.dir_log2_max; A.list_cap = t.list_cap; A.cand_cap = t.cand_cap; A.sort_cap = t.sort_cap;
@@ -425,13 +435,16 @@ static int set_tier(gwfa_ctx* ctx, KArgs& A, int ti, const int32_t* order, int32
 
 // Tiers ti0, ti0+1, ...: after each launch the queries that overflowed
 // their working memory (if any) are re-run on the next, larger tier.  When
-// `launched` the launch of tier ti0 has already been issued.
-static int run_tiers(gwfa_ctx* ctx, KArgs& A, int ti0, const int32_t* order, int32_t n, bool launched,
-                     hipStream_t st) {
+// `launched` the launch of tier ti0 has already been issued.  The first
+// tier takes the queries the screen pass listed (ctx->d_valid, their number
+// on the device); a re-run takes the retry list of the tier before.
+static int run_tiers(gwfa_ctx* ctx, KArgs& A, int ti0, int32_t n, bool launched, hipStream_t st) {
+    const int32_t* order = ctx->d_valid;
+    const int32_t* n_valid = ctx->d_valid_n;
     for (int ti = ti0; ti < N_TIERS; ++ti) {
         if (!(launched && ti == ti0)) {
             int groups = 0;
-            int rc = set_tier(ctx, A, ti, order, n, &groups);
+            int rc = set_tier(ctx, A, ti, order, n, n_valid, &groups);
             if (rc) return rc;
             HIPCHK(ctx, gwfa_launch_align(A, ctx->lanes, groups, st));
         }
@@ -443,6 +456,7 @@ static int run_tiers(gwfa_ctx* ctx, KArgs& A, int ti0, const int32_t* order, int
         ctx->rerun_total += h_retry;
         order = ctx->d_retry[ti & 1];
         n = h_retry;
+        n_valid = nullptr;
         // reset the queue and the retry counter, keep the path cursor and the dump counter
         HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, nullptr, ctx->d_retry_count, nullptr, st));
     }
@@ -465,7 +479,10 @@ static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     A.v_off_hi = d_start_hi;
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     HIPCHK(ctx, gwfa_launch_reset(ctx->d_queue, A.path_cursor, ctx->d_retry_count, A.dump_count, st));
-    return run_tiers(ctx, A, 0, d_order, n_reads, false, st);
+    A.order = d_order;
+    A.n_reads = n_reads;
+    HIPCHK(ctx, gwfa_launch_screen(A, ctx->d_valid, ctx->d_valid_n, st));
+    return run_tiers(ctx, A, 0, n_reads, false, st);
 }
 
 int gwfa_align_batch_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
@@ -537,19 +554,24 @@ int gwfa_plan_create(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     if (!p) return GWFA_ERR_NOMEM;
     p->ctx = ctx;
     p->device = ctx->device;
-    p->epoch = ctx->epoch;
     p->order = d_order;
     p->n_reads = n_reads;
     int rc = fill_args(ctx, g, n_reads, d_packed, d_read_off, d_v_start, nullptr, opts, d_res, d_path_buf,
                        path_cap, d_path_used, nullptr, 0, nullptr, p->A);
     int groups = 0;
-    if (!rc) rc = set_tier(ctx, p->A, 0, d_order, n_reads, &groups);   // allocates before the capture
+    KArgs S0 = p->A;   // the screen pass reads the caller's order
+    S0.order = d_order;
+    S0.n_reads = n_reads;
+    if (!rc) rc = set_tier(ctx, p->A, 0, ctx->d_valid, n_reads, ctx->d_valid_n, &groups);   // allocates before the capture
     if (rc) { gwfa_plan_destroy(p); return rc; }
+    p->epoch = ctx->epoch;   // after any reallocation of the context's lists
     hipError_t e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        // kernels only (no memset nodes): reset of the queue and counters, then the first tier
+        // kernels only (no memset nodes): reset of the queue and counters, the
+        // screen pass, then the first tier
         hipError_t e1 = gwfa_launch_reset(ctx->d_queue, p->A.path_cursor, ctx->d_retry_count, nullptr, p->cap);
+        if (e1 == hipSuccess) e1 = gwfa_launch_screen(S0, ctx->d_valid, ctx->d_valid_n, p->cap);
         if (e1 == hipSuccess) e1 = gwfa_launch_align(p->A, ctx->lanes, groups, p->cap);
         e = hipStreamEndCapture(p->cap, &p->graph);
         if (e1 != hipSuccess) e = e1;
@@ -581,7 +603,7 @@ int gwfa_plan_finish(gwfa_plan* p, void* hip_stream) {
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     KArgs A = p->A;
-    return run_tiers(ctx, A, 0, p->order, p->n_reads, true, st);
+    return run_tiers(ctx, A, 0, p->n_reads, true, st);
 }
 
 int gwfa_align_batch(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint8_t* reads,

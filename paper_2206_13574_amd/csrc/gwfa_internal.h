@@ -19,6 +19,7 @@ struct KArgs {
     const int32_t* v_off;            // per-query start offsets in the start vertex, or null (all 0)
     const int32_t* v_off_hi;         // per-query end of a free start window, or null (= v_off)
     const int32_t* order;            // work-queue order or null
+    const int32_t* n_valid;          // queries in `order` (written by the screen pass), or null: n_reads
     const int32_t* v_end;            // per-query end vertices (global form) or null
     int32_t end_vertex;              // end vertex of every query (global form) or -1
     int32_t n_reads;
@@ -57,6 +58,10 @@ hipError_t gwfa_launch_pack(const uint8_t* ascii, int64_t n, unsigned long long*
                             int32_t* err, hipStream_t st);
 hipError_t gwfa_launch_reset(int32_t* queue, unsigned long long* cursor, int32_t* retry_count,
                              unsigned long long* dump_count, hipStream_t st);
+// per-query parameter check before the alignment: results of the queries
+// that are out of range (GWFA_ST_BAD_INPUT), the others listed in `valid`
+// in work-queue order, their number in *n_valid
+hipError_t gwfa_launch_screen(const KArgs& A, int32_t* valid, int32_t* n_valid, hipStream_t st);
 
 // pruning network: training and batch inference (gwfa_mlp.hip)
 struct Scale8 {

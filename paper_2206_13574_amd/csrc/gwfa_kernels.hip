@@ -482,18 +482,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     gwfa_result* out = A.res + r;
     const int64_t t_begin = (int64_t)wall_clock64();
     const int64_t* __restrict__ seg_off = A.seg_off;
-    bool bad = q.vs < 0 || q.vs >= A.n_vtx || q.ve < -1 || q.ve >= A.n_vtx || (A.v_end && q.ve < 0) || q.j0 < 0 ||
-               q.j1 < q.j0;
-    if (!bad) bad = (int64_t)q.j1 > uniform64(seg_off[q.vs + 1] - seg_off[q.vs]);
-    if (bad) {
-        if (tid == 0) {
-            out->t_begin = t_begin; out->t_end = t_begin;
-            out->dist = -1; out->end_v = -1; out->end_off = -1; out->status = GWFA_ST_BAD_INPUT;
-            out->path_off = -1; out->path_len = 0; out->n_scores = 0; out->work = 0;
-            out->start_off = q.j0; out->clip = 0;
-        }
-        return;
-    }
+    // Every query here passed the screen pass (k_screen): its start vertex,
+    // start window and end vertex are in range.
     const int32_t* __restrict__ out_off = A.out_off;
     const int32_t* __restrict__ out_dst = A.out_dst;
     q.dir = reinterpret_cast<ull*>(arena + A.o_dir);
@@ -1219,15 +1209,72 @@ __global__ __launch_bounds__(BLOCK, MODE == 2 ? 2 : (BLOCK >= 512 ? 1 : 3)) void
             __syncthreads();
         }
     }
+    // queries to take: those the screen pass listed, or all of `order`
+    const int32_t n_q = A.n_valid ? __builtin_amdgcn_readfirstlane(*A.n_valid) : A.n_reads;
     for (;;) {
         if (threadIdx.x == 0) S.read = atomicAdd(A.queue, 1);
         __syncthreads();
         const int ridx = __builtin_amdgcn_readfirstlane(S.read);
         __syncthreads();
-        if (ridx >= A.n_reads) break;
+        if (ridx >= n_q) break;
         const int r = A.order ? A.order[ridx] : ridx;
         align_read<BLOCK, MODE>(A, arena, r, S);
     }
+}
+
+// Screen pass (one workgroup, before the alignment kernel): a query whose
+// start vertex, start window (0 <= j0 <= j1 <= |v_s|) or end vertex is out
+// of range gets its result here, with status GWFA_ST_BAD_INPUT; the others
+// are listed in `valid` in the work-queue order (an ordered block scan per
+// chunk of SCREEN queries), so that the alignment kernel only ever takes
+// queries whose parameters index the graph in bounds.
+constexpr int SCREEN = 1024;
+__global__ __launch_bounds__(SCREEN) void k_screen(KArgs A, int32_t* valid, int32_t* n_valid) {
+    __shared__ int32_t wsum[SCREEN / 64];
+    __shared__ int32_t base;
+    const int tid = threadIdx.x;
+    if (tid == 0) base = 0;
+    __syncthreads();
+    for (int32_t c = 0; c < A.n_reads; c += SCREEN) {
+        const int32_t idx = c + tid;
+        int ok = 0;
+        int32_t r = 0;
+        if (idx < A.n_reads) {
+            r = A.order ? A.order[idx] : idx;
+            const int32_t vs = A.v_start[r];
+            const int32_t ve = A.v_end ? A.v_end[r] : A.end_vertex;
+            const int32_t j0 = A.v_off ? A.v_off[r] : 0;
+            const int32_t j1 = A.v_off_hi ? A.v_off_hi[r] : j0;
+            bool good = vs >= 0 && vs < A.n_vtx && ve >= -1 && ve < A.n_vtx && !(A.v_end && ve < 0) && j0 >= 0 &&
+                        j1 >= j0;
+            if (good) good = (int64_t)j1 <= A.seg_off[vs + 1] - A.seg_off[vs];
+            ok = good ? 1 : 0;
+            if (!good) {
+                gwfa_result* out = A.res + r;
+                const int64_t t = (int64_t)wall_clock64();
+                out->t_begin = t; out->t_end = t;
+                out->dist = -1; out->end_v = -1; out->end_off = -1; out->status = GWFA_ST_BAD_INPUT;
+                out->path_off = -1; out->path_len = 0; out->n_scores = 0; out->work = 0;
+                out->start_off = j0; out->clip = 0;
+            }
+        }
+        // ordered exclusive scan of ok over the block
+        const ull m = __ballot(ok);
+        const int ex = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (__lane_id() == 0) wsum[tid >> 6] = __popcll(m);
+        __syncthreads();
+        int before = base, tot = 0;
+        for (int w = 0; w < SCREEN / 64; ++w) {
+            const int x = wsum[w];
+            before += (w < (tid >> 6)) ? x : 0;
+            tot += x;
+        }
+        if (ok) valid[before + ex] = r;
+        __syncthreads();
+        if (tid == 0) base += tot;
+        __syncthreads();
+    }
+    if (tid == 0) *n_valid = base;
 }
 
 // Four ASCII bases (the first in the low byte) -> 8 bits, the first base in
@@ -1335,6 +1382,12 @@ hipError_t gwfa_launch_pack(const uint8_t* ascii, int64_t n, unsigned long long*
     const int64_t blocks = (2 * n_words + tpb - 1) / tpb;   // one thread per 16 bases
     (void)hipGetLastError();
     hipLaunchKernelGGL(gwfa_dev::k_pack, dim3((unsigned)blocks), dim3(tpb), 0, st, ascii, n, out, n_words, err);
+    return hipGetLastError();
+}
+
+hipError_t gwfa_launch_screen(const KArgs& A, int32_t* valid, int32_t* n_valid, hipStream_t st) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(gwfa_dev::k_screen, dim3(1), dim3(gwfa_dev::SCREEN), 0, st, A, valid, n_valid);
     return hipGetLastError();
 }
 

