@@ -39,7 +39,13 @@
  *                   driver, extension, expansion and the pruning heuristic,
  *                   in extension mode or, with an end vertex, the global
  *                   form.  This is the oracle for the pruning heuristic and
- *                   for wavefront work counts.
+ *                   for wavefront work counts.  Pinned with pruning on
+ *                   graphs whose walks from the start all have the same
+ *                   length up to each base (there W~ is the walk position
+ *                   and an independent pairwise wavefront with the same
+ *                   keep rule must agree).  Parity unpinned: the choice of
+ *                   W~ between predecessors whose walks differ in length
+ *                   (the tie rules of the reading of W~ in Algorithm 4).
  *   orc_rev_dp      Reverse form of Eq. 1 (cost to finish from a cell), used
  *                   to label wavefront entries for the learned pruning.
  *

@@ -388,17 +388,6 @@ static int fill_args(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     if (opts->end_vertex >= g->n_vtx) return GWFA_ERR_VERTEX;
     if (d_v_end && opts->end_vertex >= 0) return GWFA_ERR_ARG;
     if (n_reads > 0 && (!d_packed || !d_read_off || !d_v_start || !d_res)) return GWFA_ERR_ARG;
-    if (ctx->retry_cap < n_reads) {
-        for (auto& p : ctx->d_retry) { if (p) (void)hipFree(p); p = nullptr; }
-        if (ctx->d_valid) (void)hipFree(ctx->d_valid);
-        ctx->d_valid = nullptr;
-        ctx->retry_cap = 0;
-        for (auto& p : ctx->d_retry)
-            if (hipMalloc((void**)&p, (size_t)n_reads * 4) != hipSuccess) return GWFA_ERR_NOMEM;
-        if (hipMalloc((void**)&ctx->d_valid, (size_t)n_reads * 4) != hipSuccess) return GWFA_ERR_NOMEM;
-        ctx->retry_cap = n_reads;
-        ctx->epoch++;   // captured plans hold the old lists
-    }
     memset(&A, 0, sizeof(A));
     A.seg = g->d_seg; A.seg_off = g->d_seg_off; A.out_off = g->d_out_off; A.out_dst = g->d_out_dst; A.n_vtx = g->n_vtx;
     A.rd = (const unsigned long long*)d_packed; A.rd_off = d_read_off; A.v_start = d_v_start;
@@ -414,6 +403,25 @@ static int fill_args(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     A.mlp_w = ctx->d_mlp; A.mlp_scale = ctx->d_mlp_scale;
     A.dir_factor = ctx->dir_factor;
     A.dump = d_dump; A.dump_cap = d_dump ? dump_cap : 0; A.dump_count = (unsigned long long*)d_dump_count;
+    return GWFA_OK;
+}
+
+// The context's per-query lists (screened queries, re-run lists) for a batch
+// of n_reads queries.
+static int ensure_lists(gwfa_ctx* ctx, int32_t n_reads) {
+    if (ctx->retry_cap >= n_reads) return GWFA_OK;
+    for (auto& p : ctx->d_retry) { if (p) (void)hipFree(p); p = nullptr; }
+    if (ctx->d_valid) (void)hipFree(ctx->d_valid);
+    ctx->d_valid = nullptr;
+    ctx->retry_cap = 0;
+    ctx->epoch++;   // captured plans hold the old lists
+    for (auto& p : ctx->d_retry)
+        if (hipMalloc((void**)&p, (size_t)n_reads * 4) != hipSuccess) { p = nullptr; return GWFA_ERR_NOMEM; }
+    if (hipMalloc((void**)&ctx->d_valid, (size_t)n_reads * 4) != hipSuccess) {
+        ctx->d_valid = nullptr;
+        return GWFA_ERR_NOMEM;
+    }
+    ctx->retry_cap = n_reads;
     return GWFA_OK;
 }
 
@@ -474,6 +482,7 @@ static int align_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     KArgs A;
     int rc = fill_args(ctx, g, n_reads, d_packed, d_read_off, d_v_start, d_v_end, opts, d_res, d_path_buf,
                        path_cap, d_path_used, d_dump, dump_cap, d_dump_count, A);
+    if (!rc) rc = ensure_lists(ctx, n_reads);
     if (rc || n_reads == 0) return rc;
     A.v_off = d_start_off;
     A.v_off_hi = d_start_hi;
@@ -558,6 +567,7 @@ int gwfa_plan_create(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     p->n_reads = n_reads;
     int rc = fill_args(ctx, g, n_reads, d_packed, d_read_off, d_v_start, nullptr, opts, d_res, d_path_buf,
                        path_cap, d_path_used, nullptr, 0, nullptr, p->A);
+    if (!rc) rc = ensure_lists(ctx, n_reads);
     int groups = 0;
     KArgs S0 = p->A;   // the screen pass reads the caller's order
     S0.order = d_order;

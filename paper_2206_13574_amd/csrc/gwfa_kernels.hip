@@ -271,7 +271,7 @@ struct Shared {
     // expansion: the entries of one batch of the source list at slots 2 ..
     // BLOCK+1 plus two neighbours on each side (slots 0, 1, BLOCK+2, BLOCK+3)
     int32_t nbv[NB], nbk[NB], nbo[NB], nbd[NB], nbw[NB], nbt[NB];
-    uint16_t mlpw[MODE >= 2 ? 4808 : 2];   // pruning network (bfloat16), loaded once per launch
+    alignas(16) uint16_t mlpw[MODE >= 2 ? 4808 : 8];   // pruning network (bfloat16), loaded once per launch
     float mscale[8];        // feature scales
 };
 
@@ -1072,12 +1072,13 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 int dropped = 0, evals = 0;
                 for (int32_t base = 0; base < n_cur; base += BLOCK) {
                     const int32_t idx = base + tid;
+                    const bool live = idx < n_cur;
                     int keep = 0;
                     int32_t ph = idx;
                     int rec = 0;
-                    float f[8];
+                    float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                     int32_t v = 0, k = 0, o = 0, W = 0, i = 0;
-                    if (idx < n_cur) {
+                    if (live) {
                         if (vmx) ph = vm_phys(vmv, idx, vm_below(vmv, idx));
                         v = Ls.v[ph]; k = Ls.k[ph]; o = Ls.o[ph]; W = Ls.w[ph];
                         i = k + o;
@@ -1085,10 +1086,12 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         entry_features(f, s, i, W, o, Lv, out_off[v + 1] - out_off[v], amax, imax, q.qlen);
                         rec = (DUMP && A.dump) ? 1 : 0;
                         keep = 1;
-                        if (run_mlp) {
+                    }
+                    if (run_mlp) {
+                        // the whole wave scores its 64 entries together (matrix cores)
+                        const float z = mlp_logit_wave(f, S.mscale, S.mlpw);
+                        if (live) {
                             ++evals;
-                            const float z = BLOCK == 64 ? mlp_logit_call(f, S.mscale, S.mlpw)
-                                                        : mlp_logit(f, S.mscale, S.mlpw);
                             keep = (z >= A.keep_threshold || i + W == amax) ? 1 : 0;   // the furthest diagonal stays
                             if (!keep) {
                                 q.pages[Ls.d[ph]].R[k & 31] = mkR(q.gen, o);   // record kept, as in Algorithm 4
@@ -1198,7 +1201,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
 // instantiation; a 512-lane workgroup fills a CU alone: it takes the whole
 // register file instead of spilling.
 template <int BLOCK, int MODE>
-__global__ __launch_bounds__(BLOCK, MODE == 2 ? 2 : (BLOCK >= 512 ? 1 : 3)) void k_align(KArgs A) {
+__global__ __launch_bounds__(BLOCK, MODE == 2 ? 2 : (BLOCK >= 512 ? 1 : (MODE == 3 ? 3 : 4))) void k_align(KArgs A) {
     constexpr bool LEARN = MODE >= 2;
     __shared__ Shared<BLOCK, MODE> S;
     char* arena = A.arena + (int64_t)blockIdx.x * A.arena_stride;

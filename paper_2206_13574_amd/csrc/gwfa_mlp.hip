@@ -152,12 +152,15 @@ __global__ __launch_bounds__(256) void k_logits(const float* __restrict__ feat, 
     __shared__ __align__(16) uint16_t sw[MLP_N + 7];
     for (int i = threadIdx.x; i < MLP_N; i += blockDim.x) sw[i] = w[i];
     __syncthreads();
+    // every lane of the wave takes part in the matrix products
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n) return;
-    float f[8];
+    float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (b < n) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) f[i] = feat[b * stride + i];
-    out[b] = mlp_logit(f, scale.s, sw);
+        for (int i = 0; i < 8; ++i) f[i] = feat[b * stride + i];
+    }
+    const float z = mlp_logit_wave(f, scale.s, sw);
+    if (b < n) out[b] = z;
 }
 
 }  // namespace gwfa_train
