@@ -268,6 +268,26 @@ int gwfa_align_dump_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, con
                         int64_t *d_path_used, float *d_dump, int64_t dump_cap, int64_t *d_dump_count,
                         void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * gwfa_align_batch_dev, but the call allocates nothing and never waits on the
+ * host.  Its working memory is a static array of 512 MiB in the library's
+ * device code, one per device, held from the library's first use on that
+ * device (the first context created there clears it) until the process
+ * ends; it holds one fixed tier of working memory (record directory of 2^14
+ * pages and wavefront lists of 8,192 entries per query), so a query that
+ * outgrows it gets GWFA_ST_ARENA and is not re-run (gwfa_align_batch_dev
+ * re-runs such queries with more memory).  At most 2^20 queries per call
+ * (GWFA_ERR_ARG beyond, with the reason in gwfa_last_error).  Launches
+ * kernels only (queue reset, screen pass, alignment) on `hip_stream`.  Every
+ * call on one device shares that device's array: calls that overlap in time
+ * on one device (from any context or thread) race and must not be issued.
+ * GWFA_ERR_DEVICE if the array could not be set up on this device. */
+int gwfa_align_batch_static_dev(gwfa_ctx *ctx, const gwfa_graph *g, int32_t n_reads, const uint64_t *d_packed,
+                                const int64_t *d_read_off, const int32_t *d_v_start, const int32_t *d_order,
+                                const gwfa_opts *opts, gwfa_result *d_res, int32_t *d_path_buf, int64_t path_cap,
+                                int64_t *d_path_used, void *hip_stream);
+
 /* Base-level alignment of each query against the walk it was aligned to: the
  * step that turns the walk of Algorithm 6 into an alignment (the paper leaves
  * it to a pairwise aligner, noting that it is cheap).  Inputs are the device

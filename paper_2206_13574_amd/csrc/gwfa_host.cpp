@@ -83,6 +83,7 @@ struct gwfa_ctx {
     size_t cig_bytes = 0;
     int32_t* d_cig_queue = nullptr;
     int n_cu = 256;
+    char* static_base = nullptr;       // the device's static working memory (gwfa_align_batch_static_dev)
     std::string err;
 };
 
@@ -229,6 +230,9 @@ int gwfa_ctx_create(int device, void* hip_stream, gwfa_ctx** out) {
                  hipDeviceSynchronize() == hipSuccess;
     if (!ok) { gwfa_ctx_destroy(c); return GWFA_ERR_NOMEM; }
     set_tiers(c, 16, 1 << 15);
+    // the static working memory of this device (looked up and cleared on the
+    // first context of the process); its entry point reports a failure here
+    c->static_base = (char*)gwfa_static_scratch(device);
     *out = c;
     return GWFA_OK;
 }
@@ -529,6 +533,60 @@ int gwfa_align_dump_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, con
     if (!d_dump || dump_cap < 0 || !d_dump_count) return GWFA_ERR_ARG;
     return align_dev(ctx, g, n_reads, d_packed, d_read_off, d_v_start, nullptr, d_order, opts, d_res, d_path_buf,
                      path_cap, d_path_used, d_dump, dump_cap, d_dump_count, hip_stream);
+}
+
+int gwfa_align_batch_static_dev(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const uint64_t* d_packed,
+                                const int64_t* d_read_off, const int32_t* d_v_start, const int32_t* d_order,
+                                const gwfa_opts* opts, gwfa_result* d_res, int32_t* d_path_buf, int64_t path_cap,
+                                int64_t* d_path_used, void* hip_stream) {
+    if (!ctx) return GWFA_ERR_ARG;
+    if (n_reads > STATIC_MAX_READS) {
+        ctx->err = "gwfa_align_batch_static_dev takes at most " + std::to_string(STATIC_MAX_READS) +
+                   " queries per call, got " + std::to_string(n_reads);
+        return GWFA_ERR_ARG;
+    }
+    if (!ctx->static_base) {
+        ctx->err = "the static working memory of this device could not be set up";
+        return GWFA_ERR_DEVICE;
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    KArgs A;
+    int rc = fill_args(ctx, g, n_reads, d_packed, d_read_off, d_v_start, nullptr, opts, d_res, d_path_buf,
+                       path_cap, d_path_used, nullptr, 0, nullptr, A);
+    if (rc || n_reads == 0) return rc;
+    // layout of the static array: header, screened list, one tier of arenas
+    char* base = ctx->static_base;
+    int32_t* queue = reinterpret_cast<int32_t*>(base);
+    int32_t* retry_count = queue + 1;
+    int32_t* n_valid = queue + 2;
+    unsigned long long* cursor = reinterpret_cast<unsigned long long*>(base + 64);
+    int32_t* valid = reinterpret_cast<int32_t*>(base + STATIC_HDR);
+    const int64_t o_arenas = align_up(STATIC_HDR + (int64_t)STATIC_MAX_READS * 4, 4096);
+    Tier t;
+    t.dir_log2_max = STATIC_DIR_LOG2;
+    t.list_cap = STATIC_LIST_CAP;
+    t.cand_cap = 2 * STATIC_LIST_CAP;
+    layout(t);
+    int per_cu = gwfa_align_blocks_per_cu(ctx->lanes);
+    if (per_cu <= 0) per_cu = 4;
+    const int64_t fit = (STATIC_BYTES - o_arenas) / t.stride;
+    const int groups = (int)std::min<int64_t>(std::min<int64_t>(fit, (int64_t)ctx->n_cu * per_cu), n_reads);
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    A.queue = queue;
+    A.retry_count = retry_count;
+    A.retry = nullptr;   // one tier: a query that overflows it keeps GWFA_ST_ARENA
+    if (!d_path_used) A.path_cursor = cursor;
+    HIPCHK(ctx, gwfa_launch_reset(queue, A.path_cursor, retry_count, nullptr, st));
+    A.order = d_order;
+    A.n_reads = n_reads;
+    HIPCHK(ctx, gwfa_launch_screen(A, valid, n_valid, st));
+    A.order = valid; A.n_valid = n_valid; A.tier = 0;
+    A.arena = base + o_arenas; A.arena_stride = t.stride;
+    A.dir_log2_max = t.dir_log2_max; A.list_cap = t.list_cap; A.cand_cap = t.cand_cap; A.sort_cap = t.sort_cap;
+    A.o_hdr = t.o_hdr; A.o_dir = t.o_dir; A.o_pages = t.o_pages; A.o_mkey = t.o_mkey;
+    A.o_tv = t.o_tv; A.o_tt = t.o_tt; A.o_lists = t.o_lists; A.o_cand = t.o_cand; A.o_sort = t.o_sort;
+    HIPCHK(ctx, gwfa_launch_align(A, ctx->lanes, groups, st));
+    return GWFA_OK;
 }
 
 struct gwfa_plan {

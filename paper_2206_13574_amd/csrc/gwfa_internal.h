@@ -58,6 +58,21 @@ hipError_t gwfa_launch_pack(const uint8_t* ascii, int64_t n, unsigned long long*
                             int32_t* err, hipStream_t st);
 hipError_t gwfa_launch_reset(int32_t* queue, unsigned long long* cursor, int32_t* retry_count,
                              unsigned long long* dump_count, hipStream_t st);
+// Working memory of the entry point that allocates nothing
+// (gwfa_align_batch_static_dev): a file-scope device array of STATIC_BYTES
+// per device holding a header (queue, counters), the screened query list
+// (at most STATIC_MAX_READS queries) and one fixed tier of per-workgroup
+// arenas (record directory of 2^STATIC_DIR_LOG2 pages, wavefront lists of
+// STATIC_LIST_CAP entries).
+constexpr int64_t STATIC_BYTES = (int64_t)512 << 20;
+constexpr int32_t STATIC_MAX_READS = 1 << 20;
+constexpr int32_t STATIC_DIR_LOG2 = 14;
+constexpr int32_t STATIC_LIST_CAP = 8192;
+constexpr int64_t STATIC_HDR = 4096;   // queue, retry counter, screened count, path cursor
+// Device address of the static array on `device` (the current device),
+// looked up and cleared once per device and process; null if that fails.
+void* gwfa_static_scratch(int device);
+
 // per-query parameter check before the alignment: results of the queries
 // that are out of range (GWFA_ST_BAD_INPUT), the others listed in `valid`
 // in work-queue order, their number in *n_valid

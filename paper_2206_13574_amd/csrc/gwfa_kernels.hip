@@ -39,6 +39,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "gwfa_internal.h"
 #include "gwfa_mlp_dev.h"
 
@@ -1326,6 +1328,17 @@ __global__ void k_pack(const uint8_t* __restrict__ ascii, int64_t n, ull* __rest
     if (bad && err) atomicExch(err, (int32_t)GWFA_ERR_ALPHABET);
 }
 
+// Working memory of the entry point that allocates nothing: one copy per
+// device, held from the library's first use on that device to the end of the
+// process.  Host code never names it directly (there it is only a stand-in
+// for the device symbol): gwfa_static_scratch looks its address up.
+static __device__ __align__(256) unsigned char scratch[STATIC_BYTES];
+
+__global__ void k_zero(ull* p, int64_t n_words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
 __global__ void k_reset(int32_t* queue, ull* path_cursor, int32_t* retry_count, ull* dump_count) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         *queue = 0;
@@ -1386,6 +1399,23 @@ hipError_t gwfa_launch_pack(const uint8_t* ascii, int64_t n, unsigned long long*
     (void)hipGetLastError();
     hipLaunchKernelGGL(gwfa_dev::k_pack, dim3((unsigned)blocks), dim3(tpb), 0, st, ascii, n, out, n_words, err);
     return hipGetLastError();
+}
+
+void* gwfa_static_scratch(int device) {
+    static std::mutex mu;
+    static void* ptr[64] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0 || device >= 64) return nullptr;
+    if (ptr[device]) return ptr[device];
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(gwfa_dev::scratch)) != hipSuccess || !p) return nullptr;
+    // generation 0 everywhere (record words of generation 0 read as "never
+    // seen"); done once, before any alignment on this device uses it
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(gwfa_dev::k_zero, dim3(2048), dim3(256), 0, nullptr, (unsigned long long*)p, STATIC_BYTES / 8);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) return nullptr;
+    ptr[device] = p;
+    return p;
 }
 
 hipError_t gwfa_launch_screen(const KArgs& A, int32_t* valid, int32_t* n_valid, hipStream_t st) {

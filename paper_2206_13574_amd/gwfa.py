@@ -70,6 +70,8 @@ _SIGS = {
                                          _i64, _P, _P]),
     "gwfa_align_dump_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _i64,
                                            _P, _P, _i64, _P, _P]),
+    "gwfa_align_batch_static_dev": (ctypes.c_int, [_P, _P, _i32, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, _P,
+                                                   _i64, _P, _P]),
     "gwfa_mlp_load": (ctypes.c_int, [_P, _P, _i64, _P]),
     "gwfa_mlp_grad_dev": (ctypes.c_int, [_P, _P, _i64, _i64, _P, _P, ctypes.c_float, _P, _P, _P, _P]),
     "gwfa_mlp_adam_dev": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _i32, ctypes.c_float, ctypes.c_float,
@@ -303,6 +305,16 @@ def align_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o:
                                      _tptr(batch.v_start), _tptr(batch.order), ctypes.byref(o), _tptr(out.res),
                                      _tptr(out.path), path_cap, _tptr(out.path_used),
                                      _P(ctx.stream.cuda_stream)), "gwfa_align_batch_dev", ctx.h)
+
+
+def align_static_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts) -> None:
+    """gwfa_align_batch_static_dev: align_dev that allocates nothing (its
+    working memory is the library's static device array)."""
+    path_cap = int(out.path.numel()) if out.path is not None else 0
+    _check(_lib.gwfa_align_batch_static_dev(ctx.h, graph.h, batch.n, _tptr(batch.packed), _tptr(batch.read_off),
+                                            _tptr(batch.v_start), _tptr(batch.order), ctypes.byref(o),
+                                            _tptr(out.res), _tptr(out.path), path_cap, _tptr(out.path_used),
+                                            _P(ctx.stream.cuda_stream)), "gwfa_align_batch_static_dev", ctx.h)
 
 
 def step_dev(ctx: Context, graph: Graph, batch: DeviceBatch, out: DeviceOut, o: Opts, v_end=None,
