@@ -96,6 +96,7 @@ struct gwfa_graph {
     int64_t* d_seg_off = nullptr;
     int32_t* d_out_off = nullptr;
     int32_t* d_out_dst = nullptr;
+    int4* d_vinfo = nullptr;           // per vertex: first out-edge, out-degree, first two targets
 };
 
 namespace {
@@ -307,6 +308,14 @@ int gwfa_graph_create(gwfa_ctx* ctx, int32_t n_vtx, const uint8_t* seq, const in
         std::vector<int32_t> fill(off.begin(), off.end() - 1);
         for (int64_t e = 0; e < n_edge; ++e) dst[fill[edge_src[e]]++] = edge_dst[e];
     }
+    // per-vertex out-edge record: one 16-byte load gives a vertex's edge range
+    // and its first two targets (most vertices of a sequence graph have at
+    // most two successors)
+    std::vector<int4> vinfo((size_t)n_vtx);
+    for (int32_t v = 0; v < n_vtx; ++v) {
+        const int32_t b = off[v], d = off[v + 1] - off[v];
+        vinfo[v] = make_int4(b, d, d > 0 ? dst[b] : -1, d > 1 ? dst[b + 1] : -1);
+    }
     gwfa_graph* g = new (std::nothrow) gwfa_graph();
     if (!g) return GWFA_ERR_NOMEM;
     g->device = ctx->device; g->n_vtx = n_vtx; g->n_edge = n_edge; g->bases = bases;
@@ -318,6 +327,7 @@ int gwfa_graph_create(gwfa_ctx* ctx, int32_t n_vtx, const uint8_t* seq, const in
               hipMalloc((void**)&g->d_seg_off, (size_t)(n_vtx + 1) * 8) == hipSuccess &&
               hipMalloc((void**)&g->d_out_off, (size_t)(n_vtx + 1) * 4) == hipSuccess &&
               hipMalloc((void**)&g->d_out_dst, dst.size() * 4) == hipSuccess &&
+              hipMalloc((void**)&g->d_vinfo, (size_t)n_vtx * sizeof(int4)) == hipSuccess &&
               hipMalloc((void**)&d_ascii, (size_t)std::max<int64_t>(bases, 1)) == hipSuccess &&
               hipMalloc((void**)&d_err, 4) == hipSuccess;
     if (!ok) {
@@ -334,6 +344,8 @@ int gwfa_graph_create(gwfa_ctx* ctx, int32_t n_vtx, const uint8_t* seq, const in
     if (e == hipSuccess) e = hipMemcpyAsync(g->d_seg_off, seq_off, (size_t)(n_vtx + 1) * 8, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(g->d_out_off, off.data(), (size_t)(n_vtx + 1) * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(g->d_out_dst, dst.data(), dst.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->d_vinfo, vinfo.data(), vinfo.size() * sizeof(int4), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(d_ascii);
     (void)hipFree(d_err);
@@ -352,6 +364,7 @@ void gwfa_graph_destroy(gwfa_graph* g) {
     if (g->d_seg_off) (void)hipFree(g->d_seg_off);
     if (g->d_out_off) (void)hipFree(g->d_out_off);
     if (g->d_out_dst) (void)hipFree(g->d_out_dst);
+    if (g->d_vinfo) (void)hipFree(g->d_vinfo);
     delete g;
 }
 
@@ -393,7 +406,8 @@ static int fill_args(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     if (d_v_end && opts->end_vertex >= 0) return GWFA_ERR_ARG;
     if (n_reads > 0 && (!d_packed || !d_read_off || !d_v_start || !d_res)) return GWFA_ERR_ARG;
     memset(&A, 0, sizeof(A));
-    A.seg = g->d_seg; A.seg_off = g->d_seg_off; A.out_off = g->d_out_off; A.out_dst = g->d_out_dst; A.n_vtx = g->n_vtx;
+    A.seg = g->d_seg; A.seg_off = g->d_seg_off; A.out_off = g->d_out_off; A.out_dst = g->d_out_dst;
+    A.vinfo = g->d_vinfo; A.n_vtx = g->n_vtx;
     A.rd = (const unsigned long long*)d_packed; A.rd_off = d_read_off; A.v_start = d_v_start;
     A.v_end = d_v_end; A.end_vertex = opts->end_vertex;
     A.res = d_res; A.path_buf = d_path_buf; A.path_cap = d_path_buf ? path_cap : 0;

@@ -11,6 +11,7 @@ struct KArgs {
     const int64_t* seg_off;          // n_vtx+1 base offsets
     const int32_t* out_off;          // n_vtx+1 CSR offsets
     const int32_t* out_dst;          // n_edge targets
+    const int4* vinfo;               // n_vtx: first out-edge index, out-degree, first and second target (-1: none)
     int32_t n_vtx;
     // queries (device)
     const unsigned long long* rd;    // packed queries

@@ -486,8 +486,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     const int64_t* __restrict__ seg_off = A.seg_off;
     // Every query here passed the screen pass (k_screen): its start vertex,
     // start window and end vertex are in range.
-    const int32_t* __restrict__ out_off = A.out_off;
     const int32_t* __restrict__ out_dst = A.out_dst;
+    const int4* __restrict__ vinfo = A.vinfo;
     q.dir = reinterpret_cast<ull*>(arena + A.o_dir);
     q.pages = reinterpret_cast<Page*>(arena + A.o_pages);
     q.mkey = reinterpret_cast<ull*>(arena + A.o_mkey);
@@ -710,10 +710,10 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         }
                     }
                     // records of the diagonals outside F_s (k-1, k+1), the windows and
-                    // v's out-edge range (needed when an output reaches the vertex end)
+                    // v's out-edge record (edge range and first targets, needed when an
+                    // output reaches the vertex end), all in one round of loads
                     const ull rw0 = (rec0 && pg0 >= 0) ? q.pages[pg0].R[(k - 1) & 31] : 0ull;
-                    const int32_t e0 = valid ? out_off[v] : 0;
-                    const int32_t e1 = valid ? out_off[v + 1] : 0;
+                    const int4 vi = valid ? vinfo[v] : make_int4(0, 0, -1, -1);
 
                     const ull rw2 = (rec2 && pg2 >= 0) ? q.pages[pg2].R[(k + 1) & 31] : 0ull;
                     const int32_t m0 = (c0 >= 0) ? min(q.qlen - (k + c0 - 1), Lv - c0) : 0;
@@ -739,14 +739,11 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     }
                     // extension of the admitted outputs
                     int32_t lx0 = 0, lx1 = 0, lx2 = 0;
-                    int32_t dst0 = -1;
                     {
                         chunks += (ov0 && m0 > 0) + (ov1 && m1 > 0) + (ov2 && m2 > 0);
                         lx0 = ov0 ? (x0 ? min((int32_t)(__clzll((long long)x0) >> 1), m0) : min(32, m0)) : 0;
                         lx1 = ov1 ? (x1 ? min((int32_t)(__clzll((long long)x1) >> 1), m1) : min(32, m1)) : 0;
                         lx2 = ov2 ? (x2 ? min((int32_t)(__clzll((long long)x2) >> 1), m2) : min(32, m2)) : 0;
-                        // the first out-edge target, fetched before the long runs below
-                        dst0 = (e1 > e0) ? out_dst[e0] : -1;
                         // whole windows matched and bases remain: continue (one call
                         // site for the three outputs keeps the register demand down)
 #pragma unroll 1
@@ -786,7 +783,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             } else if (d < 0) {
                                 atomicOr(&S.flags, F_GROW);
                             } else {
-                                const int nc = record_entry(q, S, v, kj, o, Wj, d, nw, Lv, o == Lv ? e1 - e0 : 0);
+                                const int nc = record_entry(q, S, v, kj, o, Wj, d, nw, Lv, o == Lv ? vi.y : 0);
                                 if (nc) { endm |= 1 << j; deg = nc; }
                                 Ld.v[p] = v; Ld.k[p] = kj; Ld.o[p] = o; Ld.d[p] = d;
                                 Ld.l[p] = Lv; Ld.b[p] = sb;
@@ -811,7 +808,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                                 for (int e = 0; e < deg; ++e) {
                                     const int c = cp + e;
                                     if (c < A.cand_cap) {
-                                        cu[c] = e == 0 ? dst0 : out_dst[e0 + e]; ck[c] = k2; cW[c] = Wj; ct[c] = tj;
+                                        cu[c] = e == 0 ? vi.z : (e == 1 ? vi.w : out_dst[vi.x + e]);
+                                        ck[c] = k2; cW[c] = Wj; ct[c] = tj;
                                     } else {
                                         atomicOr(&S.flags, F_LIST);
                                     }
@@ -836,7 +834,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 for (int32_t base = xlo; base < xhi; base += BLOCK) {
                     const int32_t idx = base + tid;
                     int ncr = 0;
-                    int32_t e0 = 0, k2 = 0, W = 0, t = 0, dst0 = -1;
+                    int32_t k2 = 0, W = 0, t = 0;
+                    int4 vi = make_int4(0, 0, -1, -1);
                     if (idx < xhi) {
                         // the entry carries its vertex's label (set when it was claimed),
                         // so the extension's first loads go out with the out-edge range
@@ -847,10 +846,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         W = (q.track || idx < preset_hi) ? Ld.w[idx] : 0;
                         t = (q.tb || idx < preset_hi) ? Ld.t[idx] : -1;
                         if (idx >= preset_hi && q.track) W = rval(q.pages[d].Wc[k & 31]);
-                        e0 = out_off[v];
-                        const int32_t deg = out_off[v + 1] - e0;
-                        ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, deg, chunks);
-                        if (ncr) dst0 = out_dst[e0];
+                        vi = vinfo[v];
+                        ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, vi.y, chunks);
                         // Algorithm 5's push, after the extension so that their loads overlap
                         if (idx >= preset_hi) t = q.tb ? trace_push(q, S, v, t) : -1;
                         Ld.o[idx] = o;
@@ -863,7 +860,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         for (int e = 0; e < ncr; ++e) {
                             const int c = cp + e;
                             if (c < A.cand_cap) {
-                                cu[c] = e == 0 ? dst0 : out_dst[e0 + e]; ck[c] = k2; cW[c] = W; ct[c] = t;
+                                cu[c] = e == 0 ? vi.z : (e == 1 ? vi.w : out_dst[vi.x + e]);
+                                ck[c] = k2; cW[c] = W; ct[c] = t;
                             } else {
                                 atomicOr(&S.flags, F_LIST);
                             }
@@ -1085,7 +1083,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         v = Ls.v[ph]; k = Ls.k[ph]; o = Ls.o[ph]; W = Ls.w[ph];
                         i = k + o;
                         const int32_t Lv = (int32_t)(seg_off[v + 1] - seg_off[v]);
-                        entry_features(f, s, i, W, o, Lv, out_off[v + 1] - out_off[v], amax, imax, q.qlen);
+                        entry_features(f, s, i, W, o, Lv, vinfo[v].y, amax, imax, q.qlen);
                         rec = (DUMP && A.dump) ? 1 : 0;
                         keep = 1;
                     }

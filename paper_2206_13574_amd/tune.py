@@ -108,7 +108,7 @@ def _time_config(g, sub, cfg, repeats, stream, mode: str = "exact"):
 # (a first-tier arena is about 2^dir_log2_max x 570 bytes per workgroup; the
 # library caps each tier's workgroups by its share of the free device memory)
 SPACE = dict(lanes=(128, 256, 512), groups=(512, 768, 0), list_cap=(1 << 13, 1 << 15, 1 << 16, 1 << 17),
-             dir_factor=(4, 16, 64), dir_log2_max=(15, 16, 17, 18))
+             dir_factor=(16, 64, 256), dir_log2_max=(15, 16, 17, 18))
 
 
 def autotune(workload: str, g, r, sample: int = 0, repeats: int = 2, save: bool = True, rounds: int = 2,
