@@ -3,12 +3,14 @@
 
 One step = the whole path over one batch with the queries already resident
 in HBM: ASCII -> 2-bit packing of every query on the device, then exact
-graph wavefront alignment of the batch (extension, crossings, end test,
-expansion, walk traceback) in one persistent-kernel launch.
+graph wavefront alignment of the batch (screen pass, extension, crossings,
+end test, expansion, walk traceback) in one persistent-kernel launch.
 
-Default workload: 20,000 reads (lognormal length, median 10 kb, clipped to
-1-50 kb, per-read error 0.1-5%) against a 1 Mb DAG with SNP, indel and
-structural bubbles (synthetic, seeded).  Prints ONE JSON line.
+Default workload: the largest configuration, 50,000 reads of 10-30 kb
+(per-read error 1-10%) against a 10 Mb bubble graph (SNP every ~100 bp,
+indel 1-20 bp every ~500 bp; synthetic, seeded); the 1 Mb DAG with 20,000
+lognormal reads is measured after it as a secondary figure.  Prints ONE
+JSON line.
 """
 from __future__ import annotations
 
@@ -147,12 +149,189 @@ def compare_mode(ctx, graph, batch, out, n, bases, res_exact, stream, ev, o, par
                 min_excess=int(exc.min()) if len(exc) else 0, not_ok=int((~ok).sum()))
 
 
+def measure(args, workload, steps, warmup, prune, compare):
+    """Times `steps` steps of the whole path on one workload (after `warmup`
+    untimed ones) and returns the fields of the benchmark line."""
+    import torch
+    from paper_2206_13574_amd import gwfa, tune
+
+    t0 = time.time()
+    g, r = make_workload(workload, args.reads)
+    print(f"[bench] workload {workload}: {r.n} reads, {int(r.off[-1])} bases, graph {g.n_vtx} V "
+          f"{g.n_edge} E ({time.time() - t0:.1f} s to generate)", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)          # default priority
+    ctx = gwfa.Context(0, stream=stream)
+    cfg = tune.best_config(workload)
+    if args.lanes:
+        cfg["lanes"] = args.lanes
+    if args.groups is not None:
+        cfg["groups"] = args.groups
+    ctx.config(**cfg)
+    graph = gwfa.Graph.of(ctx, g)
+    o = gwfa.opts(prune=prune, a_diff=args.a_diff, traceback=not args.no_traceback)
+    with torch.cuda.stream(stream):
+        batch = gwfa.upload_reads(ctx, r.seq, r.off, r.v_start)
+        out = gwfa.alloc_out(ctx, r.n, (int(r.off[-1]) // 4 + 64 * r.n) if o.traceback else 0)
+    torch.cuda.synchronize()
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    # the alignment of the resident batch is captured once as a HIP graph
+    # (queue reset, screen pass, persistent alignment kernel) and replayed
+    plan = gwfa.Plan(ctx, graph, batch, out, o)
+    for i in range(warmup):
+        tw = time.perf_counter()
+        gwfa.pack_dev(ctx, batch, out.err)
+        plan.launch()
+        plan.finish()
+        print(f"[bench] {workload} warm-up {i + 1}/{warmup}: {time.perf_counter() - tw:.2f} s", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    ctx.stats(reset=True)
+
+    pack_ms, align_ms = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(steps):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record(stream)
+        gwfa.pack_dev(ctx, batch, out.err)
+        e1.record(stream)
+        plan.launch()
+        plan.finish()   # re-runs of overflowed queries, if any (synchronises)
+        e2.record(stream)
+        pack_ms.append((e0, e1))
+        align_ms.append((e1, e2))
+        print(f"[bench] {workload} step {i + 1}/{steps} done at {time.perf_counter() - t_start:.2f} s",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    pack_ms = [a.elapsed_time(b) for a, b in pack_ms]
+    align_ms = [a.elapsed_time(b) for a, b in align_ms]
+    st = ctx.stats()
+    res, _, used = gwfa.fetch(out, r.n)
+    bad = int((res["status"] != 0).sum())
+    if bad:
+        print(f"[bench] WARNING: {bad} reads without status OK", file=sys.stderr)
+    if int(out.err.cpu().item()) != 0:
+        print("[bench] WARNING: alphabet error flag set", file=sys.stderr)
+
+    bases = int(r.off[-1])
+    entries = st["entries"] / steps
+    chunks = max(st["chunks"] / steps, entries)
+    cross = st["crossings"] / steps
+    admitted = st["admitted"] / steps
+    b_entry = B_ENTRY + (B_ENTRY_TB if o.traceback else 0)
+    b_cross = B_CROSS + (B_PUSH if o.traceback else 0)
+    alg_bytes = entries * b_entry + chunks * B_CHUNK + cross * b_cross
+    align_avg_s = float(np.mean(align_ms)) / 1000.0
+    achieved = alg_bytes / align_avg_s / 1e9
+    traffic, traffic_src = recorded_traffic(workload, cfg["lanes"])
+    # phases of the kernel (thread-0 wall-clock ticks summed over workgroups):
+    # the expansion with the extension of what it admits (entries, records,
+    # their compare chunks) and the crossing rounds (crossings and the
+    # extension of the crossed entries); chunks are split between the two in
+    # proportion to the entries each extends (an approximation: the kernel
+    # counts them together)
+    ticks = [st["ticks_expand"], st["ticks_rounds"], st["ticks_merge"], st["ticks_prune"]]
+    tsum = float(sum(ticks)) or 1.0
+    share_x = admitted / (admitted + cross) if admitted + cross else 1.0
+    phases = {}
+    for name, ti, nbytes in (("expand", 0, entries * b_entry + chunks * share_x * B_CHUNK),
+                             ("crossing_rounds", 1, cross * b_cross + chunks * (1 - share_x) * B_CHUNK),
+                             ("merge", 2, 0.0)):
+        sec = align_avg_s * ticks[ti] / tsum
+        phases[name] = {"time_frac": ticks[ti] / tsum, "model_bytes": nbytes,
+                        "GB/s": nbytes / sec / 1e9 if sec > 0 and nbytes else None,
+                        "frac": nbytes / sec / 1e9 / HBM_PEAK_GBS if sec > 0 and nbytes else None}
+    pack_avg_s = float(np.mean(pack_ms)) / 1000.0
+    # context for the pack's rate: a plain device copy that moves the same
+    # number of bytes (half read, half written), timed the same way
+    with torch.cuda.stream(stream):
+        half = int(bases * 1.25) // 2
+        src_t = torch.empty(half, dtype=torch.uint8, device=dev)
+        dst_t = torch.empty(half, dtype=torch.uint8, device=dev)
+        cms = []
+        for _ in range(4):
+            c0, c1 = ev(), ev()
+            c0.record(stream)
+            dst_t.copy_(src_t)
+            c1.record(stream)
+            torch.cuda.synchronize()
+            cms.append(c0.elapsed_time(c1))
+        copy_gbs = 2 * half / (float(np.median(cms[1:])) / 1000.0) / 1e9
+        del src_t, dst_t
+    pack_bytes = bases * 1.25
+    m = {
+        "value": bases * steps / wall,
+        "ms_per_step": wall * 1000.0 / steps,
+        "config": {"workload": f"{workload}: {WORKLOADS[workload]}", "reads": r.n, "bases": bases,
+                   "graph_vertices": g.n_vtx, "graph_edges": g.n_edge,
+                   "mode": ["exact", "heuristic-prune", "learned-prune"][prune],
+                   "a_diff": args.a_diff if prune == 1 else None, "traceback": bool(o.traceback),
+                   "lanes_per_read": cfg["lanes"], "groups": cfg.get("groups", 0),
+                   "dir_log2_max": cfg["dir_log2_max"], "dir_factor": cfg["dir_factor"],
+                   "list_cap": cfg["list_cap"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
+                     "kernel": "k_align (persistent, one workgroup per read)",
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": align_avg_s * 1000.0,
+                     "entries_per_launch": entries, "chunks_per_launch": chunks,
+                     "crossings_per_launch": cross, "phases": phases},
+        "pack": {"avg_ms": pack_avg_s * 1000.0, "GB/s": pack_bytes / pack_avg_s / 1e9,
+                 "frac": pack_bytes / pack_avg_s / 1e9 / HBM_PEAK_GBS,
+                 "same_traffic_copy_GB/s": copy_gbs,
+                 "frac_of_copy": pack_bytes / pack_avg_s / 1e9 / copy_gbs},
+        "reruns": st["reruns"] / steps,
+        "not_ok": bad,
+    }
+    if compare and prune == 0:
+        try:
+            # the metric's comparison: learned pruning (and Algorithm 4) on the same
+            # resident batch, outside the timed steps, against the exact distances
+            from paper_2206_13574_amd import calibrate_prune, train_prune
+            W = train_prune.load()
+            ctx.mlp_load(W["w_bf16"], W["scale"])
+            # the keep threshold calibrated on held-out sets of this workload's
+            # shape when there is one, else the training-shape threshold
+            shaped = calibrate_prune.load().get(workload)
+            tau = float(shaped["tau"]) if shaped else W["tau"]
+            tau_src = (f"held-out {workload}-shaped sets ({shaped['reads']} reads, graph seeds "
+                       f"{shaped['graph_seeds']})" if shaped else "held-out training-shaped sets")
+            # each mode at its own measured lanes per query (pruned wavefronts are
+            # small: narrower workgroups keep more queries in flight)
+            lanes_l = tune.best_lanes(workload, "learned")
+            lanes_h = tune.best_lanes(workload, "heuristic")
+            ctx.config(**dict(cfg, lanes=lanes_l))
+            learned = compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
+                                   gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=tau, mlp_gate=W["gate"],
+                                             mlp_period=W["period"], traceback=bool(o.traceback)),
+                                   dict(tau=tau, tau_calibrated_on=tau_src, gate=W["gate"], period=W["period"],
+                                        lanes=lanes_l))
+            ctx.config(**dict(cfg, lanes=lanes_h))
+            heuristic = compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
+                                     gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=50, traceback=bool(o.traceback)),
+                                     dict(a_diff=50, lanes=lanes_h))
+            m["compare"] = {"learned-prune": learned, "heuristic-prune": heuristic,
+                            "exact_align_ms": align_avg_s * 1000.0, "exact_lanes": cfg["lanes"]}
+        except Exception as e:   # the comparison must not cost the benchmark line
+            print(f"[bench] comparison legs failed: {e}", file=sys.stderr, flush=True)
+            m["compare"] = {"error": str(e)}
+    plan.close()
+    graph.close()
+    ctx.close()
+    return m, g, r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cfg4", choices=sorted(WORKLOADS))
+    ap.add_argument("--secondary", default="cfg2", choices=sorted(WORKLOADS) + ["none"],
+                    help="a second workload measured after the first (at most 5 steps), reported beside it")
     ap.add_argument("--reads", type=int, default=None)
     ap.add_argument("--lanes", type=int, default=None)
     ap.add_argument("--groups", type=int, default=None)
@@ -174,166 +353,39 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2206_13574_amd import gwfa, tune
-
-    t0 = time.time()
-    g, r = make_workload(args.workload, args.reads)
-    print(f"[bench] workload {args.workload}: {r.n} reads, {int(r.off[-1])} bases, graph {g.n_vtx} V "
-          f"{g.n_edge} E ({time.time() - t0:.1f} s to generate)", file=sys.stderr, flush=True)
-
-    dev = torch.device("cuda", 0)
-    stream = torch.cuda.Stream(device=dev)          # default priority
-    ctx = gwfa.Context(0, stream=stream)
-    cfg = tune.best_config(args.workload)
-    if args.lanes:
-        cfg["lanes"] = args.lanes
-    if args.groups is not None:
-        cfg["groups"] = args.groups
-    ctx.config(**cfg)
-    graph = gwfa.Graph.of(ctx, g)
-    o = gwfa.opts(prune=args.prune, a_diff=args.a_diff, traceback=not args.no_traceback)
-    with torch.cuda.stream(stream):
-        batch = gwfa.upload_reads(ctx, r.seq, r.off, r.v_start)
-        out = gwfa.alloc_out(ctx, r.n, (int(r.off[-1]) // 4 + 64 * r.n) if o.traceback else 0)
-    torch.cuda.synchronize()
-
-    ev = lambda: torch.cuda.Event(enable_timing=True)
-    # the alignment of the resident batch is captured once as a HIP graph
-    # (queue reset + persistent alignment kernel) and replayed every step
-    plan = gwfa.Plan(ctx, graph, batch, out, o)
-    # warmup
-    for _ in range(args.warmup):
-        gwfa.pack_dev(ctx, batch, out.err)
-        plan.launch()
-        plan.finish()
-    torch.cuda.synchronize()
-    ctx.stats(reset=True)
-
-    pack_ms, align_ms = [], []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        e0, e1, e2 = ev(), ev(), ev()
-        e0.record(stream)
-        gwfa.pack_dev(ctx, batch, out.err)
-        e1.record(stream)
-        plan.launch()
-        plan.finish()   # re-runs of overflowed queries, if any (synchronises)
-        e2.record(stream)
-        pack_ms.append((e0, e1))
-        align_ms.append((e1, e2))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    pack_ms = [a.elapsed_time(b) for a, b in pack_ms]
-    align_ms = [a.elapsed_time(b) for a, b in align_ms]
-    st = ctx.stats()
-    res, _, used = gwfa.fetch(out, r.n)
-    bad = int((res["status"] != 0).sum())
-    if bad:
-        print(f"[bench] WARNING: {bad} reads without status OK", file=sys.stderr)
-    if int(out.err.cpu().item()) != 0:
-        print("[bench] WARNING: alphabet error flag set", file=sys.stderr)
-
-    bases = int(r.off[-1])
-    ms_per_step = wall * 1000.0 / args.steps
-    value = bases * args.steps / wall
-
-    steps = args.steps
-    entries = st["entries"] / steps
-    chunks = max(st["chunks"] / steps, entries)
-    cross = st["crossings"] / steps
-    alg_bytes = entries * B_ENTRY + chunks * B_CHUNK + cross * B_CROSS
-    if o.traceback:
-        alg_bytes += entries * B_ENTRY_TB + cross * B_PUSH
-    align_avg_s = float(np.mean(align_ms)) / 1000.0
-    achieved = alg_bytes / align_avg_s / 1e9
-    traffic, traffic_src = recorded_traffic(args.workload, cfg["lanes"])
-    pack_avg_s = float(np.mean(pack_ms)) / 1000.0
-    # context for the pack's rate: a plain device copy that moves the same
-    # number of bytes (half read, half written), timed the same way
-    copy_gbs = None
-    with torch.cuda.stream(stream):
-        half = int(bases * 1.25) // 2
-        src_t = torch.empty(half, dtype=torch.uint8, device=dev)
-        dst_t = torch.empty(half, dtype=torch.uint8, device=dev)
-        cms = []
-        for _ in range(4):
-            c0, c1 = ev(), ev()
-            c0.record(stream)
-            dst_t.copy_(src_t)
-            c1.record(stream)
-            torch.cuda.synchronize()
-            cms.append(c0.elapsed_time(c1))
-        copy_gbs = 2 * half / (float(np.median(cms[1:])) / 1000.0) / 1e9
-        del src_t, dst_t
-    pack_bytes = bases * 1.25
+    m, g, r = measure(args, args.workload, args.steps, args.warmup, args.prune, not args.no_compare)
     line = {
         "metric": "query bases aligned/s on 1 GPU; exact vs learned-prune at <=1% reads over ED",
-        "value": value,
+        "value": m["value"],
         "unit": "bases/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "reads": r.n, "bases": bases,
-                   "graph_vertices": g.n_vtx, "graph_edges": g.n_edge,
-                   "mode": ["exact", "heuristic-prune", "learned-prune"][args.prune],
-                   "a_diff": args.a_diff if args.prune == 1 else None, "traceback": bool(o.traceback),
-                   "lanes_per_read": cfg["lanes"], "groups": cfg.get("groups", 0)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
-                     "kernel": "k_align (persistent, one workgroup per read)",
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": align_avg_s * 1000.0,
-                     "entries_per_launch": entries, "chunks_per_launch": chunks,
-                     "crossings_per_launch": cross},
-        "pack": {"avg_ms": pack_avg_s * 1000.0, "GB/s": pack_bytes / pack_avg_s / 1e9,
-                 "frac": pack_bytes / pack_avg_s / 1e9 / HBM_PEAK_GBS,
-                 "same_traffic_copy_GB/s": copy_gbs,
-                 "frac_of_copy": pack_bytes / pack_avg_s / 1e9 / copy_gbs if copy_gbs else None},
-        "reruns": st["reruns"] / steps,
-        "not_ok": bad,
     }
-    if args.prune == 0 and not args.no_compare:
-        try:
-            # the metric's comparison: learned pruning (and Algorithm 4) on the same
-            # resident batch, outside the timed steps, against the exact distances
-            from paper_2206_13574_amd import calibrate_prune, train_prune
-            W = train_prune.load()
-            ctx.mlp_load(W["w_bf16"], W["scale"])
-            # the keep threshold calibrated on held-out sets of this workload's
-            # shape when there is one, else the training-shape threshold
-            shaped = calibrate_prune.load().get(args.workload)
-            tau = float(shaped["tau"]) if shaped else W["tau"]
-            tau_src = (f"held-out {args.workload}-shaped sets ({shaped['reads']} reads, graph seeds "
-                       f"{shaped['graph_seeds']})" if shaped else "held-out training-shaped sets")
-            # each mode at its own measured lanes per query (pruned wavefronts are
-            # small: narrower workgroups keep more queries in flight)
-            lanes_l = tune.best_lanes(args.workload, "learned")
-            lanes_h = tune.best_lanes(args.workload, "heuristic")
-            ctx.config(**dict(cfg, lanes=lanes_l))
-            learned = compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
-                                   gwfa.opts(prune=gwfa.PRUNE_LEARNED, keep_threshold=tau, mlp_gate=W["gate"],
-                                             mlp_period=W["period"], traceback=bool(o.traceback)),
-                                   dict(tau=tau, tau_calibrated_on=tau_src, gate=W["gate"], period=W["period"],
-                                        lanes=lanes_l))
-            ctx.config(**dict(cfg, lanes=lanes_h))
-            heuristic = compare_mode(ctx, graph, batch, out, r.n, bases, res, stream, ev,
-                                     gwfa.opts(prune=gwfa.PRUNE_HEURISTIC, a_diff=50, traceback=bool(o.traceback)),
-                                     dict(a_diff=50, lanes=lanes_h))
-            line["compare"] = {"learned-prune": learned, "heuristic-prune": heuristic,
-                               "exact_align_ms": align_avg_s * 1000.0, "exact_lanes": cfg["lanes"]}
-        except Exception as e:   # the comparison must not cost the benchmark line
-            print(f"[bench] comparison legs failed: {e}", file=sys.stderr, flush=True)
-            line["compare"] = {"error": str(e)}
+    line.update({k: v for k, v in m.items() if k not in ("value", "ms_per_step")})
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(g, r, seconds=args.cpu_seconds)
+    del g, r
+    if args.secondary != "none" and args.secondary != args.workload:
+        try:
+            s, _, _ = measure(args, args.secondary, min(args.steps, 5), 1, args.prune, False)
+            line["secondary"] = {"value": s["value"], "unit": "bases/s", "ms_per_step": s["ms_per_step"],
+                                 "steps": min(args.steps, 5), "config": s["config"],
+                                 "roofline": {k: s["roofline"][k] for k in ("achieved", "frac", "avg_launch_ms",
+                                                                              "alg_bytes_per_launch")},
+                                 "not_ok": s["not_ok"]}
+        except Exception as e:   # the secondary workload must not cost the benchmark line
+            print(f"[bench] secondary workload failed: {e}", file=sys.stderr, flush=True)
+            line["secondary"] = {"error": str(e)}
     if args.copy_calib:
+        dev = torch.device("cuda", 0)
         n = 1 << 30
         a = torch.empty(n, dtype=torch.uint8, device=dev)
         b = torch.empty(n, dtype=torch.uint8, device=dev)
