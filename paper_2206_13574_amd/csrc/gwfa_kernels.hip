@@ -57,6 +57,11 @@ constexpr int F_LIST = 2;   // list / candidate capacity exceeded: re-run on a l
 // Crossing entries sorted in LDS (virtual merge) up to this many per
 // workgroup of `block` lanes; larger sets are sorted in the arena.
 constexpr int xs_lds(int block) { return block >= 256 ? 1024 : 4 * block; }
+// The expansion writes the sort key of every SAMP-th entry of the list it
+// builds into LDS (up to NSAMP keys): the merge then finds an entry's place
+// in that list by a search in LDS and one round of at most SAMP-1 loads.
+constexpr int SAMP = 8;
+constexpr int nsamp(int block) { return block >= 256 ? 1024 : 256; }
 
 
 struct Page {
@@ -270,6 +275,7 @@ struct Shared {
     int32_t sidx[XS];
     int32_t xcnt[XS];       // merge: main-list entries below each crossing entry
     ull skeys2[64];         // crossing keys sorted by rank counting (small sets)
+    ull samp[nsamp(BLOCK)]; // sort keys of list entries 0, SAMP, 2 SAMP, ... written by the expansion
     // expansion: the entries of one batch of the source list at slots 2 ..
     // BLOCK+1 plus two neighbours on each side (slots 0, 1, BLOCK+2, BLOCK+3)
     int32_t nbv[NB], nbk[NB], nbo[NB], nbd[NB], nbw[NB], nbt[NB];
@@ -391,6 +397,37 @@ __device__ __forceinline__ int32_t lower_bound_list(const Lists& L, int32_t n, u
     }
     return lo;
 }
+// The same with the list's sampled keys in LDS (samp[j] = key of entry
+// SAMP*j for j < ns): a search of the samples, then the at most SAMP-1
+// entries between two samples, loaded together.  Beyond the sampled part of
+// the list it falls back to the search in the list.
+__device__ __forceinline__ int32_t lower_bound_sampled(const Lists& L, int32_t n, ull key, const ull* samp,
+                                                       int32_t ns) {
+    int32_t lo = 0, hi = ns;                 // samples below key
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (samp[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    if (lo == 0) return 0;                   // entry 0 is not below key
+    const int32_t a = SAMP * (lo - 1) + 1;   // entry a-1 is below key
+    if (lo == ns && SAMP * ns < n) {         // past the sampled part
+        int32_t l2 = a, h2 = n;
+        while (l2 < h2) {
+            const int32_t mid = (l2 + h2) >> 1;
+            if (skey(L.v[mid], L.k[mid]) < key) l2 = mid + 1; else h2 = mid;
+        }
+        return l2;
+    }
+    const int32_t b = min(SAMP * lo, n);     // entry b is not below key (or b = n)
+    int32_t c = a;
+#pragma unroll
+    for (int32_t j = 0; j < SAMP - 1; ++j) {
+        const int32_t e = a + j;
+        if (e < b) c += skey(L.v[e], L.k[e]) < key ? 1 : 0;
+    }
+    return c;
+}
+
 // Merged view of a list whose first n1 entries are sorted and whose last m
 // entries (crossing diagonals, unsorted in memory) have known merged
 // positions xpos[0..m) (ascending) at physical slots xidx[0..m).
@@ -787,6 +824,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                                 if (nc) { endm |= 1 << j; deg = nc; }
                                 Ld.v[p] = v; Ld.k[p] = kj; Ld.o[p] = o; Ld.d[p] = d;
                                 Ld.l[p] = Lv; Ld.b[p] = sb;
+                                if ((p & (SAMP - 1)) == 0 && p < SAMP * nsamp(BLOCK)) S.samp[p / SAMP] = skey(v, kj);
                                 if (q.track) Ld.w[p] = Wj;
                                 if (q.tb) Ld.t[p] = tj;
                             }
@@ -974,6 +1012,9 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             // the next pass reads the list through that table.  Larger sets
             // are sorted in the arena and the list is rewritten merged.
             const int32_t m = ntot - n1;
+            // sampled keys of the expansion's list (none at score 0, where the
+            // list is the crossing entries of the start alone)
+            const int32_t nsl = s > 0 ? min((int32_t)nsamp(BLOCK), (n1 + SAMP - 1) / SAMP) : 0;
             vmx = 0;
             if (m > 0) {
                 if (m > A.sort_cap) { rflags = F_LIST; break; }
@@ -990,7 +1031,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         }
                         __syncthreads();
                         for (int x = tid; x < m; x += BLOCK)
-                            S.xcnt[x] = x + lower_bound_list(Ld, n1, S.skeys2[x]);
+                            S.xcnt[x] = x + lower_bound_sampled(Ld, n1, S.skeys2[x], S.samp, nsl);
                     } else {
                         int N = 1;
                         while (N < m) N <<= 1;
@@ -1001,7 +1042,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         __syncthreads();
                         bitonic<BLOCK, true>(S.skeys, S.sidx, N);
                         for (int x = tid; x < m; x += BLOCK)
-                            S.xcnt[x] = x + lower_bound_list(Ld, n1, S.skeys[x]);
+                            S.xcnt[x] = x + lower_bound_sampled(Ld, n1, S.skeys[x], S.samp, nsl);
                     }
                     __syncthreads();
                     vmx = m;
@@ -1020,7 +1061,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     for (int32_t j = tid; j < n1; j += BLOCK)
                         copy_entry(Ld, j, Lm, j + lower_bound_keys(gkeys, m, skey(Ld.v[j], Ld.k[j])), q.track, q.tb);
                     for (int32_t x = tid; x < m; x += BLOCK)
-                        copy_entry(Ld, gidx[x], Lm, x + lower_bound_list(Ld, n1, gkeys[x]), q.track, q.tb);
+                        copy_entry(Ld, gidx[x], Lm, x + lower_bound_sampled(Ld, n1, gkeys[x], S.samp, nsl), q.track,
+                                   q.tb);
                     __syncthreads();
                 }
             } else {

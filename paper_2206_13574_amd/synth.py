@@ -31,6 +31,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 ACGT = np.frombuffer(b"ACGT", dtype=np.uint8)
+# position of a byte in ACGT (as np.searchsorted(ACGT, byte)), by table
+_CODE = np.searchsorted(ACGT, np.arange(256, dtype=np.uint8))
 
 
 @dataclass
@@ -266,10 +268,10 @@ def sample_reads(g: Graph, seed: int, n_reads: int, length, err, laps=(1, 1),
         alive = np.ones(m, dtype=bool)
         segs_r, segs_v, segs_n = [], [], []
         first = np.ones(m, dtype=bool)
-        while True:
-            act = np.nonzero(alive & (need > 0))[0]
-            if len(act) == 0:
-                break
+        # the walks still growing, in ascending order (as a mask over all m
+        # would give them; the random draws below depend on that order)
+        act = np.nonzero(need > 0)[0]
+        while len(act):
             v = cur[act]
             # a self-looped vertex entered fresh gets its lap count
             fresh = selfloop[v] & (lap_left[act] == 0)
@@ -282,6 +284,7 @@ def sample_reads(g: Graph, seed: int, n_reads: int, length, err, laps=(1, 1),
             need[act] -= take
             first[act] = False
             act2 = act[need[act] > 0]
+            act = act2
             if len(act2) == 0:
                 continue
             v2 = cur[act2]
@@ -294,6 +297,8 @@ def sample_reads(g: Graph, seed: int, n_reads: int, length, err, laps=(1, 1),
                 deg = no[vv + 1] - no[vv]
                 dead = deg == 0
                 alive[mv[dead]] = False
+                if dead.any():
+                    act = act[alive[act]]
                 ok = mv[~dead]
                 if len(ok):
                     pick = (rng.random(len(ok)) * deg[~dead]).astype(np.int64)
@@ -337,7 +342,7 @@ def sample_reads(g: Graph, seed: int, n_reads: int, length, err, laps=(1, 1),
         sub = is_err & (kind == 0)
         ins = is_err & (kind == 1)
         dele = is_err & (kind == 2)
-        codes = np.searchsorted(ACGT, clean)
+        codes = _CODE[clean]
         codes = np.where(sub, (codes + rng.integers(1, 4, size=tot)) % 4, codes)
         base = ACGT[codes]
         cnt = np.where(dele, 0, np.where(ins, 2, 1))
