@@ -97,6 +97,7 @@ struct gwfa_graph {
     int32_t* d_out_off = nullptr;
     int32_t* d_out_dst = nullptr;
     int4* d_vinfo = nullptr;           // per vertex: first out-edge, out-degree, first two targets
+    int4* d_vlab = nullptr;            // per vertex: label base (low, high 32 bits), label length, 0
 };
 
 namespace {
@@ -316,6 +317,13 @@ int gwfa_graph_create(gwfa_ctx* ctx, int32_t n_vtx, const uint8_t* seq, const in
         const int32_t b = off[v], d = off[v + 1] - off[v];
         vinfo[v] = make_int4(b, d, d > 0 ? dst[b] : -1, d > 1 ? dst[b + 1] : -1);
     }
+    // per-vertex label record: one 16-byte load gives the base and length
+    // of a vertex's label in the packed store
+    std::vector<int4> vlab((size_t)n_vtx);
+    for (int32_t v = 0; v < n_vtx; ++v) {
+        const uint64_t b = (uint64_t)seq_off[v];
+        vlab[v] = make_int4((int32_t)(uint32_t)b, (int32_t)(uint32_t)(b >> 32), (int32_t)(seq_off[v + 1] - seq_off[v]), 0);
+    }
     gwfa_graph* g = new (std::nothrow) gwfa_graph();
     if (!g) return GWFA_ERR_NOMEM;
     g->device = ctx->device; g->n_vtx = n_vtx; g->n_edge = n_edge; g->bases = bases;
@@ -328,6 +336,7 @@ int gwfa_graph_create(gwfa_ctx* ctx, int32_t n_vtx, const uint8_t* seq, const in
               hipMalloc((void**)&g->d_out_off, (size_t)(n_vtx + 1) * 4) == hipSuccess &&
               hipMalloc((void**)&g->d_out_dst, dst.size() * 4) == hipSuccess &&
               hipMalloc((void**)&g->d_vinfo, (size_t)n_vtx * sizeof(int4)) == hipSuccess &&
+              hipMalloc((void**)&g->d_vlab, (size_t)n_vtx * sizeof(int4)) == hipSuccess &&
               hipMalloc((void**)&d_ascii, (size_t)std::max<int64_t>(bases, 1)) == hipSuccess &&
               hipMalloc((void**)&d_err, 4) == hipSuccess;
     if (!ok) {
@@ -346,6 +355,8 @@ int gwfa_graph_create(gwfa_ctx* ctx, int32_t n_vtx, const uint8_t* seq, const in
     if (e == hipSuccess) e = hipMemcpyAsync(g->d_out_dst, dst.data(), dst.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(g->d_vinfo, vinfo.data(), vinfo.size() * sizeof(int4), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->d_vlab, vlab.data(), vlab.size() * sizeof(int4), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(d_ascii);
     (void)hipFree(d_err);
@@ -365,6 +376,7 @@ void gwfa_graph_destroy(gwfa_graph* g) {
     if (g->d_out_off) (void)hipFree(g->d_out_off);
     if (g->d_out_dst) (void)hipFree(g->d_out_dst);
     if (g->d_vinfo) (void)hipFree(g->d_vinfo);
+    if (g->d_vlab) (void)hipFree(g->d_vlab);
     delete g;
 }
 
@@ -407,7 +419,7 @@ static int fill_args(gwfa_ctx* ctx, const gwfa_graph* g, int32_t n_reads, const 
     if (n_reads > 0 && (!d_packed || !d_read_off || !d_v_start || !d_res)) return GWFA_ERR_ARG;
     memset(&A, 0, sizeof(A));
     A.seg = g->d_seg; A.seg_off = g->d_seg_off; A.out_off = g->d_out_off; A.out_dst = g->d_out_dst;
-    A.vinfo = g->d_vinfo; A.n_vtx = g->n_vtx;
+    A.vinfo = g->d_vinfo; A.vlab = g->d_vlab; A.n_vtx = g->n_vtx;
     A.rd = (const unsigned long long*)d_packed; A.rd_off = d_read_off; A.v_start = d_v_start;
     A.v_end = d_v_end; A.end_vertex = opts->end_vertex;
     A.res = d_res; A.path_buf = d_path_buf; A.path_cap = d_path_buf ? path_cap : 0;

@@ -12,6 +12,7 @@ struct KArgs {
     const int32_t* out_off;          // n_vtx+1 CSR offsets
     const int32_t* out_dst;          // n_edge targets
     const int4* vinfo;               // n_vtx: first out-edge index, out-degree, first and second target (-1: none)
+    const int4* vlab;                // n_vtx: label base (low, high 32 bits), label length, 0
     int32_t n_vtx;
     // queries (device)
     const unsigned long long* rd;    // packed queries

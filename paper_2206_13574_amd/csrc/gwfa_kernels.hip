@@ -238,12 +238,25 @@ __device__ __forceinline__ int read_uniform(const int& x) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-// A wavefront list: per entry the diagonal (v, k), its offset o, walk length
-// W, trace index t, record page d, and the label length l and base b of v.
+// A wavefront list: per entry the diagonal (v, k), its offset o and record
+// page d in one 16-byte word, the walk length W and the trace index t in
+// arrays of their own (each moved only by the modes that use it).  The label
+// length l and base b of v are kept only for the diagonals a crossing round
+// creates (their extension in the next round then needs no lookup); every
+// other reader takes them from the graph's per-vertex label record.
 struct Lists {
-    int32_t *v, *k, *o, *w, *t, *d, *l;
+    int4* e;          // (v, k, o, d)
+    int32_t *w, *t, *l;
     int64_t* b;
 };
+// The diagonal (v, k) of entry i (the first 8 bytes of its word).
+__device__ __forceinline__ int2 vk_of(const Lists& L, int32_t i) {
+    return *reinterpret_cast<const int2*>(&L.e[i]);
+}
+// Label base of a per-vertex label record.
+__device__ __forceinline__ int64_t lab_base(int4 lab) {
+    return (int64_t)(((uint64_t)(uint32_t)lab.y << 32) | (uint32_t)lab.x);
+}
 
 // Workgroup LDS, sized for the workgroup (merge keys, the staged batch) and
 // the mode (the network's weights only where it runs).
@@ -274,7 +287,6 @@ struct Shared {
     ull skeys[XS];
     int32_t sidx[XS];
     int32_t xcnt[XS];       // merge: main-list entries below each crossing entry
-    ull skeys2[64];         // crossing keys sorted by rank counting (small sets)
     ull samp[nsamp(BLOCK)]; // sort keys of list entries 0, SAMP, 2 SAMP, ... written by the expansion
     // expansion: the entries of one batch of the source list at slots 2 ..
     // BLOCK+1 plus two neighbours on each side (slots 0, 1, BLOCK+2, BLOCK+3)
@@ -393,7 +405,8 @@ __device__ __forceinline__ int32_t lower_bound_list(const Lists& L, int32_t n, u
     int32_t lo = 0, hi = n;
     while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
-        if (skey(L.v[mid], L.k[mid]) < key) lo = mid + 1; else hi = mid;
+        const int2 a = vk_of(L, mid);
+        if (skey(a.x, a.y) < key) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
@@ -414,7 +427,8 @@ __device__ __forceinline__ int32_t lower_bound_sampled(const Lists& L, int32_t n
         int32_t l2 = a, h2 = n;
         while (l2 < h2) {
             const int32_t mid = (l2 + h2) >> 1;
-            if (skey(L.v[mid], L.k[mid]) < key) l2 = mid + 1; else h2 = mid;
+            const int2 a = vk_of(L, mid);
+            if (skey(a.x, a.y) < key) l2 = mid + 1; else h2 = mid;
         }
         return l2;
     }
@@ -423,7 +437,10 @@ __device__ __forceinline__ int32_t lower_bound_sampled(const Lists& L, int32_t n
 #pragma unroll
     for (int32_t j = 0; j < SAMP - 1; ++j) {
         const int32_t e = a + j;
-        if (e < b) c += skey(L.v[e], L.k[e]) < key ? 1 : 0;
+        if (e < b) {
+            const int2 x = vk_of(L, e);
+            c += skey(x.x, x.y) < key ? 1 : 0;
+        }
     }
     return c;
 }
@@ -461,8 +478,7 @@ __device__ __forceinline__ int32_t lower_bound_keys(const ull* keys, int32_t n, 
 // Copies entry i of a to slot j of b; W moves only when a pruning mode reads
 // it, t only when walks are traced.
 __device__ __forceinline__ void copy_entry(const Lists& a, int32_t i, const Lists& b, int32_t j, bool w, bool t) {
-    b.v[j] = a.v[i]; b.k[j] = a.k[i]; b.o[j] = a.o[i]; b.d[j] = a.d[i];
-    b.l[j] = a.l[i]; b.b[j] = a.b[i];
+    b.e[j] = a.e[i];
     if (w) b.w[j] = a.w[i];
     if (t) b.t[j] = a.t[i];
 }
@@ -535,12 +551,13 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     uint32_t* hdr = reinterpret_cast<uint32_t*>(arena + A.o_hdr);
     int32_t* const lbase = reinterpret_cast<int32_t*>(arena + A.o_lists);
     const int64_t lcap = A.list_cap;
-    // list j (0 or 1): six SoA arrays of list_cap entries
+    // list j (0 or 1): entry words, W, t, and the crossing diagonals' labels
+    // (9 words per entry of list_cap entries)
     auto LL = [&](int j) -> Lists {
         int32_t* p = lbase + (int64_t)j * 9 * lcap;
         Lists x;
-        x.v = p; x.k = p + lcap; x.o = p + 2 * lcap; x.w = p + 3 * lcap; x.t = p + 4 * lcap; x.d = p + 5 * lcap;
-        x.l = p + 6 * lcap;
+        x.e = reinterpret_cast<int4*>(p);
+        x.w = p + 4 * lcap; x.t = p + 5 * lcap; x.l = p + 6 * lcap;
         x.b = reinterpret_cast<int64_t*>(p + 7 * lcap);
         return x;
     };
@@ -595,7 +612,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 const int ds = dir_insert(q.dir, mask, dkey(q.vs, (-j) >> 5), &S.dirn);
                 if (ds < 0) atomicOr(&S.flags, F_GROW);
                 const int32_t t0 = q.tb ? trace_push(q, S, q.vs, -1 - j) : -1;
-                L0.v[t] = q.vs; L0.k[t] = -j; L0.o[t] = j; L0.w[t] = 0; L0.t[t] = t0; L0.d[t] = ds;
+                L0.e[t] = make_int4(q.vs, -j, j, ds);
+                L0.w[t] = 0; L0.t[t] = t0;
                 L0.b[t] = sb0; L0.l[t] = lv0;
             }
             if (tid == 0) {
@@ -632,6 +650,33 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 vmv.xpos = S.xcnt; vmv.xidx = S.sidx; vmv.m = vmx;
                 int32_t outbase = 0;
                 int adm = 0;
+                // each batch's entries (and, in threads 0-3, the two neighbours on
+                // each side of it) are loaded one batch ahead, before the stores
+                // of the batch being processed, so that their arrival does not
+                // wait for those stores
+                int4 pe, ph;
+                int32_t pw, pt, phw, pht;
+                auto fetch_batch = [&](int32_t bb) {
+                    pe = make_int4(-1, 0, 0, 0); pw = 0; pt = -1;
+                    const int32_t ix = bb + tid;
+                    if (ix < n) {
+                        const int32_t p0 = vmx ? vm_phys(vmv, ix, vm_below(vmv, ix)) : ix;
+                        pe = Ls.e[p0];
+                        if (q.track) pw = Ls.w[p0];
+                        if (q.tb) pt = Ls.t[p0];
+                    }
+                    ph = make_int4(-1, 0, 0, 0); phw = 0; pht = -1;
+                    if (tid < 4) {
+                        const int32_t hp = tid < 2 ? bb - 2 + tid : bb + BLOCK + (tid - 2);
+                        if (hp >= 0 && hp < n) {
+                            const int32_t pp = vmx ? vm_phys(vmv, hp, vm_below(vmv, hp)) : hp;
+                            ph = Ls.e[pp];
+                            if (q.track) phw = Ls.w[pp];
+                            if (q.tb) pht = Ls.t[pp];
+                        }
+                    }
+                };
+                fetch_batch(0);
                 for (int32_t base = 0; base < n; base += BLOCK) {
                     const int32_t idx = base + tid;
                     const bool valid = idx < n;
@@ -641,31 +686,17 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     int32_t oo1 = 0, ow1 = 0, ot1 = 0, od1 = -1;
                     int32_t oo2 = 0, ow2 = 0, ot2 = 0, od2 = -1; bool on2 = false;
                     // this lane's entry (merged position idx); v = -1 past the end
-                    int32_t v = -1, k = 0, o0 = 0, ds0 = 0, W0 = 0, t0 = -1, Lv = 0;
-                    int64_t sb = 0;
-                    if (valid) {
-                        const int32_t p0 = vmx ? vm_phys(vmv, idx, vm_below(vmv, idx)) : idx;
-                        v = Ls.v[p0]; k = Ls.k[p0]; o0 = Ls.o[p0]; ds0 = Ls.d[p0];
-                        Lv = Ls.l[p0]; sb = Ls.b[p0];
-                        if (q.track) W0 = Ls.w[p0];
-                        if (q.tb) t0 = Ls.t[p0];
-                    }
+                    const int32_t v = pe.x, k = pe.y, o0 = pe.z, ds0 = pe.w, W0 = pw, t0 = pt;
+                    // the label of v (its length bounds the candidates, its base places
+                    // their windows), requested before the exchange of neighbours,
+                    // which hides its latency
+                    const int4 lab = valid ? A.vlab[v] : make_int4(0, 0, 0, 0);
                     // the neighbours at merged positions idx-2 .. idx+2 come from LDS:
-                    // every lane stages its entry, threads 0-3 load the two positions
-                    // on each side of the batch (in the same round as their own)
+                    // every lane stages its entry, threads 0-3 the two positions on
+                    // each side of the batch
                     {
-                        int32_t hv = -1, hk = 0, ho = 0, hd = 0, hw = 0, ht = -1;
-                        int hs = 0;
-                        if (tid < 4) {
-                            const int32_t hp = tid < 2 ? base - 2 + tid : base + BLOCK + (tid - 2);
-                            hs = tid < 2 ? tid : BLOCK + tid;
-                            if (hp >= 0 && hp < n) {
-                                const int32_t pp = vmx ? vm_phys(vmv, hp, vm_below(vmv, hp)) : hp;
-                                hv = Ls.v[pp]; hk = Ls.k[pp]; ho = Ls.o[pp]; hd = Ls.d[pp];
-                                if (q.track) hw = Ls.w[pp];
-                                if (q.tb) ht = Ls.t[pp];
-                            }
-                        }
+                        const int32_t hv = ph.x, hk = ph.y, ho = ph.z, hd = ph.w, hw = phw, ht = pht;
+                        const int hs = tid < 2 ? tid : BLOCK + tid;
                         S.nbv[tid + 2] = v; S.nbk[tid + 2] = k; S.nbo[tid + 2] = o0; S.nbd[tid + 2] = ds0;
                         if (q.track) S.nbw[tid + 2] = W0;
                         if (q.tb) S.nbt[tid + 2] = t0;
@@ -676,6 +707,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         }
                     }
                     lds_barrier();
+                    const int32_t Lv = lab.z;
+                    const int64_t sb = lab_base(lab);
                     const int32_t vm1 = S.nbv[tid + 1], km1 = S.nbk[tid + 1];
                     const int32_t vm2 = S.nbv[tid], km2 = S.nbk[tid];
                     const int32_t vp1 = S.nbv[tid + 3], kp1 = S.nbk[tid + 3], op1 = S.nbo[tid + 3];
@@ -797,6 +830,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     const int cnt = (int)ov0 + (int)ov1 + (int)ov2;
                     int total;
                     const int pos = block_excl_scan<BLOCK>(cnt, total, S.scan);
+                    if (base + BLOCK < n) fetch_batch(base + BLOCK);
                     adm += cnt;
                     int slot = 0;
                     int endm = 0;        // outputs that reached the vertex end (cross every out-edge)
@@ -822,8 +856,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             } else {
                                 const int nc = record_entry(q, S, v, kj, o, Wj, d, nw, Lv, o == Lv ? vi.y : 0);
                                 if (nc) { endm |= 1 << j; deg = nc; }
-                                Ld.v[p] = v; Ld.k[p] = kj; Ld.o[p] = o; Ld.d[p] = d;
-                                Ld.l[p] = Lv; Ld.b[p] = sb;
+                                Ld.e[p] = make_int4(v, kj, o, d);
                                 if ((p & (SAMP - 1)) == 0 && p < SAMP * nsamp(BLOCK)) S.samp[p / SAMP] = skey(v, kj);
                                 if (q.track) Ld.w[p] = Wj;
                                 if (q.tb) Ld.t[p] = tj;
@@ -877,8 +910,9 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     if (idx < xhi) {
                         // the entry carries its vertex's label (set when it was claimed),
                         // so the extension's first loads go out with the out-edge range
-                        const int32_t v = Ld.v[idx], k = Ld.k[idx], d = Ld.d[idx];
-                        int32_t o = Ld.o[idx];
+                        const int4 e = Ld.e[idx];
+                        const int32_t v = e.x, k = e.y, d = e.w;
+                        int32_t o = e.z;
                         const int64_t sb = Ld.b[idx];
                         const int32_t Lv = Ld.l[idx];
                         W = (q.track || idx < preset_hi) ? Ld.w[idx] : 0;
@@ -888,7 +922,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, vi.y, chunks);
                         // Algorithm 5's push, after the extension so that their loads overlap
                         if (idx >= preset_hi) t = q.tb ? trace_push(q, S, v, t) : -1;
-                        Ld.o[idx] = o;
+                        Ld.e[idx].z = o;
                         if (q.track) Ld.w[idx] = W;
                         if (q.tb) Ld.t[idx] = t;
                         k2 = k + Lv;
@@ -947,7 +981,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     const int pos = wave_alloc(claim, &S.n_out);
                     if (claim) {
                         if (pos < A.list_cap) {
-                            Ld.v[pos] = cu[c]; Ld.k[pos] = ck[c]; Ld.o[pos] = 0; Ld.d[pos] = ds;
+                            Ld.e[pos] = make_int4(cu[c], ck[c], 0, ds);
                             Ld.l[pos] = cLv; Ld.b[pos] = csb;
                             if (q.track) Ld.w[pos] = cW[c];
                             if (q.tb) Ld.t[pos] = ct[c];
@@ -982,8 +1016,9 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 if (q.ilo < q.qlen) {
                     // the end cells of row iend (all of them are in this score's list)
                     for (int32_t idx = tid; idx < ntot; idx += BLOCK) {
-                        const int32_t v = Ld.v[idx], o = Ld.o[idx];
-                        if (Ld.k[idx] + o == iend && ends_walk(q, v, o, Ld.l[idx]))
+                        const int4 e = Ld.e[idx];
+                        const int32_t v = e.x, o = e.z;
+                        if (e.y + o == iend && ends_walk(q, v, o, A.vlab[v].z))
                             atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
                     }
                     __syncthreads();
@@ -992,8 +1027,10 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     if (tid == 0) S.tend = -1;
                     __syncthreads();
                     const int32_t ev = (int32_t)(S.endkey >> 32), eo = (int32_t)(S.endkey & 0xffffffffull);
-                    for (int32_t idx = tid; idx < ntot; idx += BLOCK)
-                        if (Ld.v[idx] == ev && Ld.o[idx] == eo && Ld.k[idx] + eo == iend) S.tend = Ld.t[idx];
+                    for (int32_t idx = tid; idx < ntot; idx += BLOCK) {
+                        const int4 e = Ld.e[idx];
+                        if (e.x == ev && e.z == eo && e.y + eo == iend) S.tend = Ld.t[idx];
+                    }
                     __syncthreads();
                 }
                 break;
@@ -1006,7 +1043,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             if (ntot == 0) { status = q.ve >= 0 ? GWFA_ST_UNREACHABLE : GWFA_ST_MAX_SCORE; break; }
             if (q.ve < 0 && s > q.qlen + 1) { status = GWFA_ST_MAX_SCORE; break; }
             // ========== merge the crossing diagonals into the sorted list ==========
-            // Small sets (<= Shared::XS) are merged virtually: their keys are sorted
+            // Small sets (<= Shared::XS) are merged virtually: their keys are ranked
             // in LDS and each gets its merged position (its rank among the
             // crossing keys plus the number of expansion outputs below it);
             // the next pass reads the list through that table.  Larger sets
@@ -1019,30 +1056,21 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             if (m > 0) {
                 if (m > A.sort_cap) { rflags = F_LIST; break; }
                 if (m <= Shared<BLOCK, MODE>::XS) {
-                    if (m <= 64) {
-                        for (int i = tid; i < m; i += BLOCK) S.skeys[i] = skey(Ld.v[n1 + i], Ld.k[n1 + i]);
-                        __syncthreads();
-                        for (int i = tid; i < m; i += BLOCK) {
-                            const ull ki = S.skeys[i];
-                            int32_t rk = 0;
-                            for (int j = 0; j < m; ++j) rk += S.skeys[j] < ki;
-                            S.skeys2[rk] = ki;
-                            S.sidx[rk] = n1 + i;
-                        }
-                        __syncthreads();
-                        for (int x = tid; x < m; x += BLOCK)
-                            S.xcnt[x] = x + lower_bound_sampled(Ld, n1, S.skeys2[x], S.samp, nsl);
-                    } else {
-                        int N = 1;
-                        while (N < m) N <<= 1;
-                        for (int i = tid; i < N; i += BLOCK) {
-                            S.skeys[i] = (i < m) ? skey(Ld.v[n1 + i], Ld.k[n1 + i]) : ~0ull;
-                            S.sidx[i] = n1 + i;
-                        }
-                        __syncthreads();
-                        bitonic<BLOCK, true>(S.skeys, S.sidx, N);
-                        for (int x = tid; x < m; x += BLOCK)
-                            S.xcnt[x] = x + lower_bound_sampled(Ld, n1, S.skeys[x], S.samp, nsl);
+                    // rank of each crossing key among them (the keys are distinct
+                    // diagonals), counted against every key read from LDS by all
+                    // lanes at once: two barriers, where a sorting network would
+                    // take one per stage
+                    for (int i = tid; i < m; i += BLOCK) {
+                        const int2 a = vk_of(Ld, n1 + i);
+                        S.skeys[i] = skey(a.x, a.y);
+                    }
+                    __syncthreads();
+                    for (int i = tid; i < m; i += BLOCK) {
+                        const ull ki = S.skeys[i];
+                        int32_t rk = 0;
+                        for (int j = 0; j < m; ++j) rk += S.skeys[j] < ki ? 1 : 0;
+                        S.sidx[rk] = n1 + i;
+                        S.xcnt[rk] = rk + lower_bound_sampled(Ld, n1, ki, S.samp, nsl);
                     }
                     __syncthreads();
                     vmx = m;
@@ -1052,14 +1080,21 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     while (N < m) N <<= 1;
                     if (N > A.sort_cap) { rflags = F_LIST; break; }
                     for (int i = tid; i < N; i += BLOCK) {
-                        gkeys[i] = (i < m) ? skey(Ld.v[n1 + i], Ld.k[n1 + i]) : ~0ull;
+                        ull key = ~0ull;
+                        if (i < m) {
+                            const int2 a = vk_of(Ld, n1 + i);
+                            key = skey(a.x, a.y);
+                        }
+                        gkeys[i] = key;
                         gidx[i] = n1 + i;
                     }
                     __syncthreads();
                     bitonic<BLOCK, false>(gkeys, gidx, N);
                     const Lists Lm = LL(cur);
-                    for (int32_t j = tid; j < n1; j += BLOCK)
-                        copy_entry(Ld, j, Lm, j + lower_bound_keys(gkeys, m, skey(Ld.v[j], Ld.k[j])), q.track, q.tb);
+                    for (int32_t j = tid; j < n1; j += BLOCK) {
+                        const int2 a = vk_of(Ld, j);
+                        copy_entry(Ld, j, Lm, j + lower_bound_keys(gkeys, m, skey(a.x, a.y)), q.track, q.tb);
+                    }
                     for (int32_t x = tid; x < m; x += BLOCK)
                         copy_entry(Ld, gidx[x], Lm, x + lower_bound_sampled(Ld, n1, gkeys[x], S.samp, nsl), q.track,
                                    q.tb);
@@ -1084,10 +1119,11 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     int32_t ph = idx;
                     if (idx < n_cur) {
                         if (vmx) ph = vm_phys(vmv, idx, vm_below(vmv, idx));
-                        const int32_t a = Ls.k[ph] + Ls.o[ph] + Ls.w[ph];
+                        const int4 e = Ls.e[ph];
+                        const int32_t a = e.y + e.z + Ls.w[ph];
                         keep = (amax - a < A.a_diff) ? 1 : 0;
                         if (!keep) {   // the diagonal keeps its offset as its record
-                            q.pages[Ls.d[ph]].R[Ls.k[ph] & 31] = mkR(q.gen, Ls.o[ph]);
+                            q.pages[e.w].R[e.y & 31] = mkR(q.gen, e.z);
                             ++dropped;
                         }
                     }
@@ -1119,12 +1155,13 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     int32_t ph = idx;
                     int rec = 0;
                     float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                    int32_t v = 0, k = 0, o = 0, W = 0, i = 0;
+                    int32_t v = 0, k = 0, o = 0, dp = 0, W = 0, i = 0;
                     if (live) {
                         if (vmx) ph = vm_phys(vmv, idx, vm_below(vmv, idx));
-                        v = Ls.v[ph]; k = Ls.k[ph]; o = Ls.o[ph]; W = Ls.w[ph];
+                        const int4 e = Ls.e[ph];
+                        v = e.x; k = e.y; o = e.z; dp = e.w; W = Ls.w[ph];
                         i = k + o;
-                        const int32_t Lv = (int32_t)(seg_off[v + 1] - seg_off[v]);
+                        const int32_t Lv = A.vlab[v].z;
                         entry_features(f, s, i, W, o, Lv, vinfo[v].y, amax, imax, q.qlen);
                         rec = (DUMP && A.dump) ? 1 : 0;
                         keep = 1;
@@ -1136,7 +1173,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             ++evals;
                             keep = (z >= A.keep_threshold || i + W == amax) ? 1 : 0;   // the furthest diagonal stays
                             if (!keep) {
-                                q.pages[Ls.d[ph]].R[k & 31] = mkR(q.gen, o);   // record kept, as in Algorithm 4
+                                q.pages[dp].R[k & 31] = mkR(q.gen, o);   // record kept, as in Algorithm 4
                                 ++dropped;
                             }
                         }
