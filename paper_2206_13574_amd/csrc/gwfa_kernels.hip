@@ -62,6 +62,11 @@ constexpr int xs_lds(int block) { return block >= 256 ? 1024 : 4 * block; }
 // in that list by a search in LDS and one round of at most SAMP-1 loads.
 constexpr int SAMP = 8;
 constexpr int nsamp(int block) { return block >= 256 ? 1024 : 256; }
+// The exact mode stages the crossing rounds' data in LDS: up to xstage(block)
+// diagonals claimed by one round (read back by the next round's extension)
+// and up to twice as many crossing candidates (read back by the claims); the
+// rest goes through the arena.
+constexpr int xstage(int block) { return block >= 512 ? 256 : (block >= 256 ? 128 : 64); }
 
 
 struct Page {
@@ -95,13 +100,17 @@ __device__ __forceinline__ ull win32(const ull* __restrict__ w, int64_t p) {
 
 // LCP of q[qp ...] and label[sp ...], at most lim bases.  Each step
 // compares up to four consecutive 32-base windows; they share words (window j
-// spans words j and j+1 of the step), so a step loads at most five words per
+// spans words j and j+1 of the step), so a step loads five words per
 // sequence, all issued together: a long exact run costs one memory round trip
-// per 128 bases.  Words past the range are not loaded (both stores end with
-// two words of padding, so a window starting inside the range stays in
-// bounds).
-__device__ __forceinline__ int32_t lcp(const ull* __restrict__ qw, int64_t qp, const ull* __restrict__ sw,
-                                       int64_t sp, int32_t lim, uint32_t& chunks) {
+// per 128 bases.  Word indices are clamped to qmax / smax, the word after the
+// one holding the range's last base (both stores end with two words of
+// padding, so that word exists): a window that starts inside the range never
+// reaches past it, and the words clamped are never used.
+// ALL = false loads only the words the step needs (fewer registers in
+// flight, for call sites where registers are scarce).
+template <bool ALL = true>
+__device__ __forceinline__ int32_t lcp(const ull* __restrict__ qw, int64_t qp, int64_t qmax, const ull* __restrict__ sw,
+                                       int64_t sp, int64_t smax, int32_t lim, uint32_t& chunks) {
     int32_t l = 0;
     const int qs = (int)((qp & 31) * 2), ss = (int)((sp & 31) * 2);
     while (l < lim) {
@@ -110,10 +119,14 @@ __device__ __forceinline__ int32_t lcp(const ull* __restrict__ qw, int64_t qp, c
         ull a[5], b[5];
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            // word j is needed by windows j-1 and j
-            const bool need = 32 * (j - 1) < rem;
-            a[j] = need ? qw[qi + j] : 0ull;
-            b[j] = need ? sw[si + j] : 0ull;
+            if (ALL) {
+                a[j] = qw[min(qi + j, qmax)];
+                b[j] = sw[min(si + j, smax)];
+            } else {
+                const bool need = 32 * (j - 1) < rem;   // word j is needed by windows j-1 and j
+                a[j] = need ? qw[qi + j] : 0ull;
+                b[j] = need ? sw[si + j] : 0ull;
+            }
         }
         int32_t m = 0;
         bool stop = false;
@@ -147,10 +160,12 @@ __device__ int dir_find(const ull* __restrict__ dir, uint32_t mask, ull key) {
 }
 
 // Find-or-insert; counts insertions in *n_ins.  -1 when the table is full.
-__device__ int dir_insert(ull* dir, uint32_t mask, ull key, int* n_ins) {
-    uint32_t h = dhash(key) & mask;
+// The same, continuing from `c`, a value read from slot h earlier (it may be
+// stale: a slot only ever goes from empty to a key, and an empty slot is
+// claimed by compare-and-swap, which sees the current value).
+__device__ int dir_settle(ull* dir, uint32_t mask, ull key, uint32_t h, ull c, int* n_ins) {
     for (uint32_t p = 0; p <= mask; ++p) {
-        const ull c = __hip_atomic_load(&dir[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p > 0) c = __hip_atomic_load(&dir[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (c == key) return (int)h;
         if (c == 0) {
             const ull old = atomicCAS(&dir[h], 0ull, key);
@@ -160,6 +175,10 @@ __device__ int dir_insert(ull* dir, uint32_t mask, ull key, int* n_ins) {
         h = (h + 1) & mask;
     }
     return -1;
+}
+__device__ __forceinline__ int dir_insert(ull* dir, uint32_t mask, ull key, int* n_ins) {
+    const uint32_t h = dhash(key) & mask;
+    return dir_settle(dir, mask, key, h, __hip_atomic_load(&dir[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), n_ins);
 }
 
 // Exclusive prefix sum of x >= 0 over the 64 lanes of the wave, plus the
@@ -264,6 +283,8 @@ template <int BLOCK, int MODE>
 struct Shared {
     static constexpr int XS = xs_lds(BLOCK);
     static constexpr int NB = BLOCK + 4;
+    static constexpr int XC = MODE == 0 ? xstage(BLOCK) : 0;       // claimed diagonals staged
+    static constexpr int CS = MODE == 0 ? 2 * xstage(BLOCK) : 0;   // crossing candidates staged
     int32_t read;
     int32_t n_out;    // entries in the list being built (outputs, then crossing entries)
     int32_t ncand;
@@ -291,6 +312,12 @@ struct Shared {
     // expansion: the entries of one batch of the source list at slots 2 ..
     // BLOCK+1 plus two neighbours on each side (slots 0, 1, BLOCK+2, BLOCK+3)
     int32_t nbv[NB], nbk[NB], nbo[NB], nbd[NB], nbw[NB], nbt[NB];
+    // crossing rounds: claimed diagonals (vertex, diagonal, page, label length,
+    // predecessor's trace index, label base) and candidates (target, diagonal,
+    // trace index of the crossing diagonal)
+    int32_t xsv[XC + 1], xsk[XC + 1], xsd[XC + 1], xsl[XC + 1], xst[XC + 1];
+    int64_t xsb[XC + 1];
+    int32_t csu[CS + 1], csk[CS + 1], cst[CS + 1];
     alignas(16) uint16_t mlpw[MODE >= 2 ? 4808 : 8];   // pruning network (bfloat16), loaded once per launch
     float mscale[8];        // feature scales
 };
@@ -314,11 +341,21 @@ struct Q {
     bool tb, track;   // traced walks; walk lengths and lags tracked (pruning, dumps)
 };
 
+template <class SH>
+__device__ __forceinline__ int32_t trace_push_from(const Q& q, SH& S, int32_t v, int32_t tprev, ull probe);
 // Algorithm 5: T gets (v, t) unless the pair is already there; the index of
 // the pair's slot in the de-duplication map is its trace index.
 template <class SH>
 __device__ __forceinline__ int32_t trace_push(const Q& q, SH& S, int32_t v, int32_t tprev) {
-    const int ms = dir_insert(q.mkey, q.mask, dkey(v, tprev), &S.mn);
+    return trace_push_from(q, S, v, tprev,
+                           __hip_atomic_load(&q.mkey[dhash(dkey(v, tprev)) & q.mask], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT));
+}
+// The same, given the value an earlier read found in the pair's first map
+// slot (so that the read can go out with other loads).
+template <class SH>
+__device__ __forceinline__ int32_t trace_push_from(const Q& q, SH& S, int32_t v, int32_t tprev, ull probe) {
+    const int ms = dir_settle(q.mkey, q.mask, dkey(v, tprev), dhash(dkey(v, tprev)) & q.mask, probe, &S.mn);
     if (ms < 0) { atomicOr(&S.flags, F_GROW); return -1; }
     // the slot's (v, tprev) is fixed by its key, so every inserter may write it
     q.Tv[ms] = v;
@@ -372,7 +409,7 @@ __device__ __forceinline__ int extend_entry(const KArgs& A, const Q& q, SH& S, i
                                             int32_t Lv, int32_t deg, uint32_t& chunks) {
     const int32_t i = k + o;
     const int32_t lim = min(q.qlen - i, Lv - o);
-    const int32_t l = lcp(q.rd, q.q0 + i, A.seg, sb + o, lim, chunks);
+    const int32_t l = lcp(q.rd, q.q0 + i, ((q.q0 + q.qlen) >> 5) + 1, A.seg, sb + o, ((sb + Lv) >> 5) + 1, lim, chunks);
     o += l;
     W += l;
     return record_entry(q, S, v, k, o, W, d, mark, Lv, deg);
@@ -434,13 +471,13 @@ __device__ __forceinline__ int32_t lower_bound_sampled(const Lists& L, int32_t n
     }
     const int32_t b = min(SAMP * lo, n);     // entry b is not below key (or b = n)
     int32_t c = a;
+    // every lane loads all SAMP-1 keys (indices clamped to the list), so that
+    // the loads go out together
 #pragma unroll
     for (int32_t j = 0; j < SAMP - 1; ++j) {
         const int32_t e = a + j;
-        if (e < b) {
-            const int2 x = vk_of(L, e);
-            c += skey(x.x, x.y) < key ? 1 : 0;
-        }
+        const int2 x = vk_of(L, min(e, n - 1));
+        c += (e < b && skey(x.x, x.y) < key) ? 1 : 0;
     }
     return c;
 }
@@ -519,6 +556,7 @@ __device__ __forceinline__ void entry_features(float* f, int32_t s, int32_t i, i
 // are not allocated.
 template <int BLOCK, int MODE>
 __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shared<BLOCK, MODE>& S) {
+    using SH = Shared<BLOCK, MODE>;
     constexpr bool LEARN = MODE >= 2;
     constexpr bool DUMP = MODE == 2;
     const int tid = threadIdx.x;
@@ -690,7 +728,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     // the label of v (its length bounds the candidates, its base places
                     // their windows), requested before the exchange of neighbours,
                     // which hides its latency
-                    const int4 lab = valid ? A.vlab[v] : make_int4(0, 0, 0, 0);
+                    const int4 lab = A.vlab[valid ? v : 0];   // unconditional: its wait can move to the first use
                     // the neighbours at merged positions idx-2 .. idx+2 come from LDS:
                     // every lane stages its entry, threads 0-3 the two positions on
                     // each side of the batch
@@ -781,17 +819,25 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     }
                     // records of the diagonals outside F_s (k-1, k+1), the windows and
                     // v's out-edge record (edge range and first targets, needed when an
-                    // output reaches the vertex end), all in one round of loads
-                    const ull rw0 = (rec0 && pg0 >= 0) ? q.pages[pg0].R[(k - 1) & 31] : 0ull;
-                    const int4 vi = valid ? vinfo[v] : make_int4(0, 0, -1, -1);
-
-                    const ull rw2 = (rec2 && pg2 >= 0) ? q.pages[pg2].R[(k + 1) & 31] : 0ull;
+                    // output reaches the vertex end), all in one round of loads: every
+                    // lane loads every word (one without a use reads a harmless valid
+                    // address), so that no load sits in a branch of its own and the
+                    // loads are waited for once
                     const int32_t m0 = (c0 >= 0) ? min(q.qlen - (k + c0 - 1), Lv - c0) : 0;
                     const int32_t m1 = (c1 >= 0) ? min(q.qlen - (k + c1), Lv - c1) : 0;
                     const int32_t m2 = (c2 >= 0) ? min(q.qlen - (k + 1 + c2), Lv - c2) : 0;
-                    const ull x0 = (m0 > 0) ? (win32(q.rd, q.q0 + k - 1 + c0) ^ win32(A.seg, sb + c0)) : 0ull;
-                    const ull x1 = (m1 > 0) ? (win32(q.rd, q.q0 + k + c1) ^ win32(A.seg, sb + c1)) : 0ull;
-                    const ull x2 = (m2 > 0) ? (win32(q.rd, q.q0 + k + 1 + c2) ^ win32(A.seg, sb + c2)) : 0ull;
+                    const ull rw0l = q.pages[(rec0 && pg0 >= 0) ? pg0 : 0].R[(k - 1) & 31];
+                    const ull rw2l = q.pages[(rec2 && pg2 >= 0) ? pg2 : 0].R[(k + 1) & 31];
+                    const int4 vil = vinfo[valid ? v : 0];
+                    const ull x0l = win32(q.rd, m0 > 0 ? q.q0 + k - 1 + c0 : q.q0) ^ win32(A.seg, m0 > 0 ? sb + c0 : 0);
+                    const ull x1l = win32(q.rd, m1 > 0 ? q.q0 + k + c1 : q.q0) ^ win32(A.seg, m1 > 0 ? sb + c1 : 0);
+                    const ull x2l = win32(q.rd, m2 > 0 ? q.q0 + k + 1 + c2 : q.q0) ^ win32(A.seg, m2 > 0 ? sb + c2 : 0);
+                    const ull rw0 = (rec0 && pg0 >= 0) ? rw0l : 0ull;
+                    const ull rw2 = (rec2 && pg2 >= 0) ? rw2l : 0ull;
+                    const int4 vi = valid ? vil : make_int4(0, 0, -1, -1);
+                    const ull x0 = (m0 > 0) ? x0l : 0ull;
+                    const ull x1 = (m1 > 0) ? x1l : 0ull;
+                    const ull x2 = (m2 > 0) ? x2l : 0ull;
                     if (c0 >= 0) {
                         const bool rec = rgen(rw0) == q.gen;
                         if (!rec || c0 > rval(rw0)) {
@@ -822,7 +868,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             const int32_t mj = (j == 0) ? m0 : ((j == 1) ? m1 : m2);
                             if (lj == 32 && mj > 32) {
                                 const int32_t oj = (j == 0) ? oo0 : ((j == 1) ? oo1 : oo2);
-                                const int32_t r = 32 + lcp(q.rd, q.q0 + k - 1 + j + oj + 32, A.seg, sb + oj + 32, mj - 32, chunks);
+                                const int32_t r = 32 + lcp<false>(q.rd, q.q0 + k - 1 + j + oj + 32, ((q.q0 + q.qlen) >> 5) + 1, A.seg,
+                                                           sb + oj + 32, ((sb + Lv) >> 5) + 1, mj - 32, chunks);
                                 if (j == 0) lx0 = r; else if (j == 1) lx1 = r; else lx2 = r;
                             }
                         }
@@ -878,9 +925,11 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                                 const int32_t k2 = k - 1 + j + Lv;
                                 for (int e = 0; e < deg; ++e) {
                                     const int c = cp + e;
-                                    if (c < A.cand_cap) {
-                                        cu[c] = e == 0 ? vi.z : (e == 1 ? vi.w : out_dst[vi.x + e]);
-                                        ck[c] = k2; cW[c] = Wj; ct[c] = tj;
+                                    const int32_t u = e == 0 ? vi.z : (e == 1 ? vi.w : out_dst[vi.x + e]);
+                                    if (c < SH::CS) {
+                                        S.csu[c] = u; S.csk[c] = k2; S.cst[c] = tj;
+                                    } else if (c < A.cand_cap) {
+                                        cu[c] = u; ck[c] = k2; cW[c] = Wj; ct[c] = tj;
                                     } else {
                                         atomicOr(&S.flags, F_LIST);
                                     }
@@ -910,18 +959,29 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     if (idx < xhi) {
                         // the entry carries its vertex's label (set when it was claimed),
                         // so the extension's first loads go out with the out-edge range
-                        const int4 e = Ld.e[idx];
-                        const int32_t v = e.x, k = e.y, d = e.w;
-                        int32_t o = e.z;
-                        const int64_t sb = Ld.b[idx];
-                        const int32_t Lv = Ld.l[idx];
-                        W = (q.track || idx < preset_hi) ? Ld.w[idx] : 0;
-                        t = (q.tb || idx < preset_hi) ? Ld.t[idx] : -1;
+                        int32_t v, k, d, o, Lv;
+                        int64_t sb;
+                        if (round > 0 && idx - xlo < SH::XC) {   // claimed by the previous round, at offset 0
+                            const int32_t j = idx - xlo;
+                            v = S.xsv[j]; k = S.xsk[j]; d = S.xsd[j]; o = 0; Lv = S.xsl[j]; sb = S.xsb[j];
+                            t = q.tb ? S.xst[j] : -1;
+                        } else {
+                            const int4 e = Ld.e[idx];
+                            v = e.x; k = e.y; d = e.w; o = e.z;
+                            sb = Ld.b[idx];
+                            Lv = Ld.l[idx];
+                            W = (q.track || idx < preset_hi) ? Ld.w[idx] : 0;
+                            t = (q.tb || idx < preset_hi) ? Ld.t[idx] : -1;
+                        }
                         if (idx >= preset_hi && q.track) W = rval(q.pages[d].Wc[k & 31]);
                         vi = vinfo[v];
+                        // Algorithm 5's push: its map slot is read with the extension's
+                        // loads, the push itself follows the extension
+                        const bool push = q.tb && idx >= preset_hi;
+                        const ull tprobe = __hip_atomic_load(&q.mkey[push ? (dhash(dkey(v, t)) & q.mask) : 0],
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, vi.y, chunks);
-                        // Algorithm 5's push, after the extension so that their loads overlap
-                        if (idx >= preset_hi) t = q.tb ? trace_push(q, S, v, t) : -1;
+                        if (idx >= preset_hi) t = push ? trace_push_from(q, S, v, t, tprobe) : -1;
                         Ld.e[idx].z = o;
                         if (q.track) Ld.w[idx] = W;
                         if (q.tb) Ld.t[idx] = t;
@@ -931,9 +991,11 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         const int cp = wave_alloc(ncr, &S.ncand);
                         for (int e = 0; e < ncr; ++e) {
                             const int c = cp + e;
-                            if (c < A.cand_cap) {
-                                cu[c] = e == 0 ? vi.z : (e == 1 ? vi.w : out_dst[vi.x + e]);
-                                ck[c] = k2; cW[c] = W; ct[c] = t;
+                            const int32_t u = e == 0 ? vi.z : (e == 1 ? vi.w : out_dst[vi.x + e]);
+                            if (c < SH::CS) {
+                                S.csu[c] = u; S.csk[c] = k2; S.cst[c] = t;
+                            } else if (c < A.cand_cap) {
+                                cu[c] = u; ck[c] = k2; cW[c] = W; ct[c] = t;
                             } else {
                                 atomicOr(&S.flags, F_LIST);
                             }
@@ -956,16 +1018,26 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     int ds = -1;
                     int64_t csb = 0;
                     int32_t cLv = 0;
+                    int32_t u = 0, kc = 0, wc = 0, tc = -1;
                     if (c < nc) {
-                        // the target's label, stored with the entry when it is claimed
-                        const int32_t u = cu[c];
-                        csb = seg_off[u];
-                        cLv = (int32_t)(seg_off[u + 1] - csb);
-                        ds = dir_insert(q.dir, mask, dkey(u, ck[c] >> 5), &S.dirn);
+                        if (c < SH::CS) {
+                            u = S.csu[c]; kc = S.csk[c]; tc = S.cst[c];
+                        } else {
+                            u = cu[c]; kc = ck[c]; wc = cW[c]; tc = ct[c];
+                        }
+                        // the target's label (stored with the entry when it is claimed)
+                        // and the directory slot, read together
+                        const ull key = dkey(u, kc >> 5);
+                        const uint32_t h = dhash(key) & mask;
+                        const ull probe = __hip_atomic_load(&q.dir[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const int4 lab = A.vlab[u];
+                        csb = lab_base(lab);
+                        cLv = lab.z;
+                        ds = dir_settle(q.dir, mask, key, h, probe, &S.dirn);
                         if (ds < 0) {
                             atomicOr(&S.flags, F_GROW);
                         } else {
-                            ull* rp = &q.pages[ds].R[ck[c] & 31];
+                            ull* rp = &q.pages[ds].R[kc & 31];
                             const ull w = __hip_atomic_load(rp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             bool part = false;
                             if (rgen(w) != q.gen) {
@@ -975,16 +1047,20 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             } else if (w == mine) {
                                 part = true;
                             }
-                            if (part && q.track) atomicMax(&q.pages[ds].Wc[ck[c] & 31], mkR(q.gen, cW[c]));
+                            if (part && q.track) atomicMax(&q.pages[ds].Wc[kc & 31], mkR(q.gen, wc));
                         }
                     }
                     const int pos = wave_alloc(claim, &S.n_out);
                     if (claim) {
                         if (pos < A.list_cap) {
-                            Ld.e[pos] = make_int4(cu[c], ck[c], 0, ds);
+                            Ld.e[pos] = make_int4(u, kc, 0, ds);
                             Ld.l[pos] = cLv; Ld.b[pos] = csb;
-                            if (q.track) Ld.w[pos] = cW[c];
-                            if (q.tb) Ld.t[pos] = ct[c];
+                            if (q.track) Ld.w[pos] = wc;
+                            if (q.tb) Ld.t[pos] = tc;
+                            const int32_t j = pos - xhi;
+                            if (j < SH::XC) {
+                                S.xsv[j] = u; S.xsk[j] = kc; S.xsd[j] = ds; S.xsl[j] = cLv; S.xsb[j] = csb; S.xst[j] = tc;
+                            }
                         } else {
                             atomicOr(&S.flags, F_LIST);
                         }
@@ -1280,7 +1356,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
 // instantiation; a 512-lane workgroup fills a CU alone: it takes the whole
 // register file instead of spilling.
 template <int BLOCK, int MODE>
-__global__ __launch_bounds__(BLOCK, MODE == 2 ? 2 : (BLOCK >= 512 ? 1 : (MODE == 3 ? 3 : 4))) void k_align(KArgs A) {
+__global__ __launch_bounds__(BLOCK, MODE == 2 ? 2 : (BLOCK >= 512 ? (MODE == 0 ? 4 : 1) : (MODE == 3 ? 3 : 4))) void k_align(KArgs A) {
     constexpr bool LEARN = MODE >= 2;
     __shared__ Shared<BLOCK, MODE> S;
     char* arena = A.arena + (int64_t)blockIdx.x * A.arena_stride;
