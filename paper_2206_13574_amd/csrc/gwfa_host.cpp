@@ -146,7 +146,7 @@ int ensure_tier(gwfa_ctx* ctx, int ti) {
 
 // Share of the device memory free at configuration time that each tier's
 // arenas may take (all three can be allocated at once).
-constexpr double TIER_SHARE[N_TIERS] = {0.45, 0.30, 0.10};
+constexpr double TIER_SHARE[N_TIERS] = {0.60, 0.20, 0.05};
 
 void set_tiers(gwfa_ctx* ctx, int32_t dir_log2_max, int32_t list_cap) {
     // default: as many persistent workgroups as can be resident at once
