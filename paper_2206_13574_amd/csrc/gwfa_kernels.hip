@@ -1025,12 +1025,20 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         } else {
                             u = cu[c]; kc = ck[c]; wc = cW[c]; tc = ct[c];
                         }
-                        // the target's label (stored with the entry when it is claimed)
-                        // and the directory slot, read together
+                        // the target's label (stored with the entry when it is claimed),
+                        // the directory slot and the record word in the page of that
+                        // slot, read together: the page is almost always at its key's
+                        // home slot (found there, or inserted there), and only when it
+                        // is not is the record read again from the slot found.  The
+                        // early read sees what a later one would: in this phase the
+                        // word changes only by the claims' compare-and-swaps, which
+                        // compare against the value read.
                         const ull key = dkey(u, kc >> 5);
                         const uint32_t h = dhash(key) & mask;
                         const ull probe = __hip_atomic_load(&q.dir[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         const int4 lab = A.vlab[u];
+                        const ull wh = __hip_atomic_load(&q.pages[h].R[kc & 31], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
                         csb = lab_base(lab);
                         cLv = lab.z;
                         ds = dir_settle(q.dir, mask, key, h, probe, &S.dirn);
@@ -1038,7 +1046,9 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             atomicOr(&S.flags, F_GROW);
                         } else {
                             ull* rp = &q.pages[ds].R[kc & 31];
-                            const ull w = __hip_atomic_load(rp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            const ull w = (ds == (int)h) ? wh
+                                                         : __hip_atomic_load(rp, __ATOMIC_RELAXED,
+                                                                             __HIP_MEMORY_SCOPE_AGENT);
                             bool part = false;
                             if (rgen(w) != q.gen) {
                                 const ull old = atomicCAS(rp, w, mine);
