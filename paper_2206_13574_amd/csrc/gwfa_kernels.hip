@@ -415,6 +415,38 @@ __device__ __forceinline__ int extend_entry(const KArgs& A, const Q& q, SH& S, i
     return record_entry(q, S, v, k, o, W, d, mark, Lv, deg);
 }
 
+// Crossing candidate c: target u, diagonal k2 in u, walk length W, trace
+// index t.  The first SH::CS (exact mode) go to LDS, the rest to the arena.
+template <class SH>
+__device__ __forceinline__ void put_cand(SH& S, const KArgs& A, int32_t* cu, int32_t* ck, int32_t* cW, int32_t* ct,
+                                         int c, int32_t u, int32_t k2, int32_t W, int32_t t) {
+    if (c < SH::CS) {
+        S.csu[c] = u; S.csk[c] = k2; S.cst[c] = t;
+    } else if (c < A.cand_cap) {
+        cu[c] = u; ck[c] = k2; cW[c] = W; ct[c] = t;
+    } else {
+        atomicOr(&S.flags, F_LIST);
+    }
+}
+// The candidates for the out-edges of a vertex whose out-edge record is vi
+// (first edge, degree, first two targets), from slot c on.  Only the edges
+// after the second need loads, in a branch of their own that ends by waiting
+// for them: with a load inside the loop over all edges, or one possibly in
+// flight after it, the compiler made the wave wait for every outstanding
+// memory operation (the output stores and the next batch's entries among
+// them) before each candidate, on every vertex.
+template <class SH>
+__device__ __forceinline__ void put_out_edges(SH& S, const KArgs& A, int32_t* cu, int32_t* ck, int32_t* cW,
+                                              int32_t* ct, int c, int4 vi, int32_t k2, int32_t W, int32_t t) {
+    const int deg = vi.y;
+    if (deg > 0) put_cand(S, A, cu, ck, cW, ct, c, vi.z, k2, W, t);
+    if (deg > 1) put_cand(S, A, cu, ck, cW, ct, c + 1, vi.w, k2, W, t);
+    if (deg > 2) {
+        for (int e = 2; e < deg; ++e) put_cand(S, A, cu, ck, cW, ct, c + e, A.out_dst[vi.x + e], k2, W, t);
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): no load of this branch outlives it
+    }
+}
+
 // Bitonic sort of n keys (+ payload) in place, ascending; n is a power of 2.
 // LDS=true when keys and payload are in LDS (stages then need LDS barriers only).
 template <int BLOCK, bool LDS>
@@ -484,23 +516,15 @@ __device__ __forceinline__ int32_t lower_bound_sampled(const Lists& L, int32_t n
 
 // Merged view of a list whose first n1 entries are sorted and whose last m
 // entries (crossing diagonals, unsorted in memory) have known merged
-// positions xpos[0..m) (ascending) at physical slots xidx[0..m).
-struct VMerge {
-    const int32_t* xpos;
-    const int32_t* xidx;
-    int32_t m;
-};
-// number of crossing entries whose merged position is below p
-__device__ __forceinline__ int32_t vm_below(const VMerge& vm, int32_t p) {
-    int32_t lo = 0, hi = vm.m;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (vm.xpos[mid] < p) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-__device__ __forceinline__ int32_t vm_phys(const VMerge& vm, int32_t p, int32_t c) {
-    return (c < vm.m && vm.xpos[c] == p) ? vm.xidx[c] : p - c;
+// positions: a bitmap over the merged positions (bit p of word p >> 5 set when
+// position p holds a crossing entry), the number of bits set below each word,
+// and the physical slots of the crossing entries in merged order.  The slot of
+// merged position p takes two independent LDS reads and a count.
+__device__ __forceinline__ int32_t vm_phys_bm(const uint32_t* bm, const int32_t* pre, const int32_t* xidx, int32_t p) {
+    const uint32_t word = bm[p >> 5];
+    const int b = p & 31;
+    const int32_t c = pre[p >> 5] + __popc(word & ((1u << b) - 1u));
+    return ((word >> b) & 1u) ? xidx[c] : p - c;
 }
 
 __device__ __forceinline__ int32_t lower_bound_keys(const ull* keys, int32_t n, ull key) {
@@ -616,6 +640,8 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
     int cur = 1;
     int32_t n_cur = 0;
     int32_t vmx = 0;          // crossing entries of the source list merged virtually
+    uint32_t* const vm_bits = reinterpret_cast<uint32_t*>(S.skeys);
+    int32_t* const vm_pre = reinterpret_cast<int32_t*>(S.skeys) + SH::XS;
     int64_t work = 0;
     uint32_t chunks = 0;
     for (;;) {   // attempts with a growing directory
@@ -684,8 +710,6 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                 // ========== EXPAND (Algorithm 3) + EXTEND of what it admits ==========
                 const Lists Ls = LL(cur);
                 const int32_t n = n_cur;
-                VMerge vmv;
-                vmv.xpos = S.xcnt; vmv.xidx = S.sidx; vmv.m = vmx;
                 int32_t outbase = 0;
                 int adm = 0;
                 // each batch's entries (and, in threads 0-3, the two neighbours on
@@ -698,7 +722,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     pe = make_int4(-1, 0, 0, 0); pw = 0; pt = -1;
                     const int32_t ix = bb + tid;
                     if (ix < n) {
-                        const int32_t p0 = vmx ? vm_phys(vmv, ix, vm_below(vmv, ix)) : ix;
+                        const int32_t p0 = vmx ? vm_phys_bm(vm_bits, vm_pre, S.sidx, ix) : ix;
                         pe = Ls.e[p0];
                         if (q.track) pw = Ls.w[p0];
                         if (q.tb) pt = Ls.t[p0];
@@ -707,7 +731,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     if (tid < 4) {
                         const int32_t hp = tid < 2 ? bb - 2 + tid : bb + BLOCK + (tid - 2);
                         if (hp >= 0 && hp < n) {
-                            const int32_t pp = vmx ? vm_phys(vmv, hp, vm_below(vmv, hp)) : hp;
+                            const int32_t pp = vmx ? vm_phys_bm(vm_bits, vm_pre, S.sidx, hp) : hp;
                             ph = Ls.e[pp];
                             if (q.track) phw = Ls.w[pp];
                             if (q.tb) pht = Ls.t[pp];
@@ -923,17 +947,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                                 const int32_t Wj = ((j == 0) ? ow0 : ((j == 1) ? ow1 : ow2)) + lj;
                                 const int32_t tj = (j == 0) ? ot0 : ((j == 1) ? ot1 : ot2);
                                 const int32_t k2 = k - 1 + j + Lv;
-                                for (int e = 0; e < deg; ++e) {
-                                    const int c = cp + e;
-                                    const int32_t u = e == 0 ? vi.z : (e == 1 ? vi.w : out_dst[vi.x + e]);
-                                    if (c < SH::CS) {
-                                        S.csu[c] = u; S.csk[c] = k2; S.cst[c] = tj;
-                                    } else if (c < A.cand_cap) {
-                                        cu[c] = u; ck[c] = k2; cW[c] = Wj; ct[c] = tj;
-                                    } else {
-                                        atomicOr(&S.flags, F_LIST);
-                                    }
-                                }
+                                put_out_edges(S, A, cu, ck, cW, ct, cp, vi, k2, Wj, tj);
                                 cp += deg;
                             }
                         }
@@ -989,17 +1003,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     }
                     if (__ballot(ncr != 0)) {
                         const int cp = wave_alloc(ncr, &S.ncand);
-                        for (int e = 0; e < ncr; ++e) {
-                            const int c = cp + e;
-                            const int32_t u = e == 0 ? vi.z : (e == 1 ? vi.w : out_dst[vi.x + e]);
-                            if (c < SH::CS) {
-                                S.csu[c] = u; S.csk[c] = k2; S.cst[c] = t;
-                            } else if (c < A.cand_cap) {
-                                cu[c] = u; ck[c] = k2; cW[c] = W; ct[c] = t;
-                            } else {
-                                atomicOr(&S.flags, F_LIST);
-                            }
-                        }
+                        if (ncr) put_out_edges(S, A, cu, ck, cW, ct, cp, vi, k2, W, t);
                     }
                 }
                 __syncthreads();
@@ -1129,11 +1133,12 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             if (ntot == 0) { status = q.ve >= 0 ? GWFA_ST_UNREACHABLE : GWFA_ST_MAX_SCORE; break; }
             if (q.ve < 0 && s > q.qlen + 1) { status = GWFA_ST_MAX_SCORE; break; }
             // ========== merge the crossing diagonals into the sorted list ==========
-            // Small sets (<= Shared::XS) are merged virtually: their keys are ranked
-            // in LDS and each gets its merged position (its rank among the
-            // crossing keys plus the number of expansion outputs below it);
-            // the next pass reads the list through that table.  Larger sets
-            // are sorted in the arena and the list is rewritten merged.
+            // Small sets (<= Shared::XS, in lists of up to 32 Shared::XS entries)
+            // are merged virtually: their keys are ranked in LDS and each gets
+            // its merged position (its rank among the crossing keys plus the
+            // number of expansion outputs below it); the next pass reads the list
+            // through a bitmap of those positions.  Larger sets are sorted in the
+            // arena and the list is rewritten merged.
             const int32_t m = ntot - n1;
             // sampled keys of the expansion's list (none at score 0, where the
             // list is the crossing entries of the start alone)
@@ -1141,7 +1146,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             vmx = 0;
             if (m > 0) {
                 if (m > A.sort_cap) { rflags = F_LIST; break; }
-                if (m <= Shared<BLOCK, MODE>::XS) {
+                if (m <= SH::XS && ntot <= 32 * SH::XS) {
                     // rank of each crossing key among them (the keys are distinct
                     // diagonals), counted against every key read from LDS by all
                     // lanes at once: two barriers, where a sorting network would
@@ -1159,6 +1164,31 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         S.xcnt[rk] = rk + lower_bound_sampled(Ld, n1, ki, S.samp, nsl);
                     }
                     __syncthreads();
+                    // the merged positions as a bitmap over the list plus the number of
+                    // bits below each word, in the keys' storage (no longer needed;
+                    // 32 positions per key slot): the passes over this list find an
+                    // entry's physical slot from two words
+                    {
+                        const int32_t nw = (ntot + 31) >> 5;
+                        for (int32_t w = tid; w < nw; w += BLOCK) vm_bits[w] = 0u;
+                        lds_barrier();
+                        for (int32_t j = tid; j < m; j += BLOCK) {
+                            const int32_t pj = S.xcnt[j];
+                            atomicOr(&vm_bits[pj >> 5], 1u << (pj & 31));
+                        }
+                        lds_barrier();
+                        const int32_t kw = (nw + BLOCK - 1) / BLOCK;   // words per thread, in order
+                        const int32_t w0 = min(tid * kw, nw), w1 = min(w0 + kw, nw);
+                        int nbits = 0;
+                        for (int32_t w = w0; w < w1; ++w) nbits += __popc(vm_bits[w]);
+                        int tot;
+                        int below = block_excl_scan<BLOCK>(nbits, tot, S.scan);
+                        for (int32_t w = w0; w < w1; ++w) {
+                            vm_pre[w] = below;
+                            below += __popc(vm_bits[w]);
+                        }
+                        lds_barrier();
+                    }
                     vmx = m;
                     cur = nb;
                 } else {
@@ -1195,8 +1225,6 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             if ((MODE == 1 || MODE == 2) && A.prune == GWFA_PRUNE_HEURISTIC && amax > A.a_diff) {
                 const Lists Ls = LL(cur);
                 const Lists Lp = LL(1 - cur);
-                VMerge vmv;
-                vmv.xpos = S.xcnt; vmv.xidx = S.sidx; vmv.m = vmx;
                 int32_t outbase = 0;
                 int dropped = 0;
                 for (int32_t base = 0; base < n_cur; base += BLOCK) {
@@ -1204,7 +1232,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     int keep = 0;
                     int32_t ph = idx;
                     if (idx < n_cur) {
-                        if (vmx) ph = vm_phys(vmv, idx, vm_below(vmv, idx));
+                        if (vmx) ph = vm_phys_bm(vm_bits, vm_pre, S.sidx, idx);
                         const int4 e = Ls.e[ph];
                         const int32_t a = e.y + e.z + Ls.w[ph];
                         keep = (amax - a < A.a_diff) ? 1 : 0;
@@ -1230,8 +1258,6 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             if (LEARN && ((DUMP && A.dump) || run_mlp)) {
                 const Lists Ls = LL(cur);
                 const Lists Lp = LL(1 - cur);
-                VMerge vmv;
-                vmv.xpos = S.xcnt; vmv.xidx = S.sidx; vmv.m = vmx;
                 int32_t outbase = 0;
                 int dropped = 0, evals = 0;
                 for (int32_t base = 0; base < n_cur; base += BLOCK) {
@@ -1243,7 +1269,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                     int32_t v = 0, k = 0, o = 0, dp = 0, W = 0, i = 0;
                     if (live) {
-                        if (vmx) ph = vm_phys(vmv, idx, vm_below(vmv, idx));
+                        if (vmx) ph = vm_phys_bm(vm_bits, vm_pre, S.sidx, idx);
                         const int4 e = Ls.e[ph];
                         v = e.x; k = e.y; o = e.z; dp = e.w; W = Ls.w[ph];
                         i = k + o;
