@@ -1159,7 +1159,17 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                     for (int i = tid; i < m; i += BLOCK) {
                         const ull ki = S.skeys[i];
                         int32_t rk = 0;
-                        for (int j = 0; j < m; ++j) rk += S.skeys[j] < ki ? 1 : 0;
+                        // sixteen keys per step, read together (one LDS round trip per
+                        // step instead of one per key)
+                        int j = 0;
+                        for (; j + 16 <= m; j += 16) {
+                            ull x[16];
+#pragma unroll
+                            for (int u = 0; u < 16; ++u) x[u] = S.skeys[j + u];
+#pragma unroll
+                            for (int u = 0; u < 16; ++u) rk += x[u] < ki ? 1 : 0;
+                        }
+                        for (; j < m; ++j) rk += S.skeys[j] < ki ? 1 : 0;
                         S.sidx[rk] = n1 + i;
                         S.xcnt[rk] = rk + lower_bound_sampled(Ld, n1, ki, S.samp, nsl);
                     }
