@@ -204,7 +204,9 @@ __device__ __forceinline__ int wave_alloc(int cnt, int* counter) {
     const int ex = wave_excl_scan(cnt, total);
     int base = 0;
     if (__lane_id() == 0 && total > 0) base = atomicAdd(counter, total);
-    base = __shfl(base, 0, 64);
+    // lane 0's value to every lane: a lane read (one ALU instruction), not a
+    // permute through LDS
+    base = __builtin_amdgcn_readlane(base, 0);
     return base + ex;
 }
 
