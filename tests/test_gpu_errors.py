@@ -5,8 +5,10 @@ between existing vertices), argument and option errors of the host-buffer
 and device entry points (all returned before any kernel is launched), the
 per-query status of `opts.max_score`, and the global form with one end
 vertex shared by a batch (`opts.end_vertex`) against the dense oracle.
-Queries whose start vertex, start window or end vertex is out of range are
-covered by the skipped tests named in the design notes."""
+Queries whose start vertex, start window or end vertex is out of range get
+a per-query status (GWFA_ST_BAD_INPUT from the screen pass) in
+tests/test_gpu_parity.py, tests/test_gpu_start.py and
+tests/test_gpu_global.py."""
 import numpy as np
 import pytest
 
