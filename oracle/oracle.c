@@ -43,9 +43,13 @@
  *                   graphs whose walks from the start all have the same
  *                   length up to each base (there W~ is the walk position
  *                   and an independent pairwise wavefront with the same
- *                   keep rule must agree).  Parity unpinned: the choice of
- *                   W~ between predecessors whose walks differ in length
- *                   (the tie rules of the reading of W~ in Algorithm 4).
+ *                   keep rule must agree).  Where walks differ in length,
+ *                   every W~ is pinned as the length of a real walk that
+ *                   aligns the consumed query prefix at no more than the
+ *                   entry's score (Eq. 1 with the walk length as an extra
+ *                   index), and the tie rules between such walks (a choice
+ *                   the paper leaves open) against an independent
+ *                   implementation of the same rules.
  *   orc_rev_dp      Reverse form of Eq. 1 (cost to finish from a cell), used
  *                   to label wavefront entries for the learned pruning.
  *

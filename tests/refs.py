@@ -554,3 +554,173 @@ def spell_cols(rng, cols) -> bytes:
         c = sorted(c)
         out.append(c[int(rng.integers(0, len(c)))])
     return bytes(out)
+
+
+# ---------------------------------------------------------------------------
+# Walk lengths W~ on graphs whose walks differ in length (indels, loops).
+#
+# (1) A soundness reference from Eq. 1 with the walk length as an extra
+#     index: C[i][w][p] = the least cost of aligning q[1..i] to a walk string
+#     of exactly w bases that starts at the start cell and ends at base
+#     position p.  A front cell reached at score s along a chain of
+#     expansions (cost 1) and extensions / crossings (cost 0) has a walk of
+#     length W~ with an alignment of cost s, so C[i][W~][p] <= s; in the
+#     exact form the front cell's Eq. 1 value is s, so equality holds.
+# (2) The tie rules of the reading of W~ (the larger W~ between candidates
+#     of one diagonal with the same offset; crossings grouped in rounds, the
+#     larger W~ within a round, an earlier round first) re-implemented with
+#     per-score dictionaries and explicit crossing layers.
+# ---------------------------------------------------------------------------
+def walk_length_costs(labels, edges, q: bytes, v_s: int, w_max: int, j0: int = 0):
+    """Returns (C, pos) with C of shape (|q|+1, w_max+1, P+1): P base
+    positions (v, j), j = 1..|v|, indexed by pos[(v, j)], and index P the
+    start when j0 = 0 (with j0 >= 1 the start is the position (v_s, j0))."""
+    q = q.upper()
+    labs = [l.upper() for l in labels]
+    pos = {}
+    for v, s in enumerate(labs):
+        for j in range(1, len(s) + 1):
+            pos[(v, j)] = len(pos)
+    P = len(pos)
+    start = P if j0 == 0 else pos[(v_s, j0)]
+    INF = 1 << 30
+    preds = [[] for _ in range(P)]
+    base = np.zeros(P, dtype=np.uint8)
+    for (v, j), p in pos.items():
+        base[p] = ord(labs[v][j - 1])
+        if j >= 2:
+            preds[p].append(pos[(v, j - 1)])
+        else:
+            preds[p] += [pos[(u, len(labs[u]))] for u, b in edges if b == v]
+            if v == v_s and j0 == 0:
+                preds[p].append(P)
+    width = max(1, max(len(x) for x in preds))
+    pm = np.full((P, width), P + 1, dtype=np.int64)     # P + 1: an always-infinite pad slot
+    for p, x in enumerate(preds):
+        pm[p, :len(x)] = sorted(set(x))
+    n = len(q)
+    C = np.full((n + 1, w_max + 1, P + 2), INF, dtype=np.int64)
+    C[0, 0, start] = 0
+    qa = np.frombuffer(q, dtype=np.uint8)
+    for i in range(n + 1):
+        for w in range(w_max + 1):
+            row = C[i, w]
+            if i > 0:
+                np.minimum(row, C[i - 1, w] + 1, out=row)                       # query base alone
+            if w > 0:
+                prev = C[i, w - 1][pm].min(axis=1)
+                np.minimum(row[:P], prev + 1, out=row[:P])                       # walk base alone
+                if i > 0:
+                    diag = C[i - 1, w - 1][pm].min(axis=1) + (base != qa[i - 1])
+                    np.minimum(row[:P], diag, out=row[:P])                       # match / substitution
+            row[P + 1] = INF
+    return C[:, :, :P + 1], pos
+
+
+def front_cell_cost(C, pos, labels, edges, v_s: int, j0: int, i: int, v: int, off: int, W: int) -> int:
+    """Least cost over walks of exactly W bases ending at the front cell
+    (v, off): the base position (v, off) when off >= 1; with off = 0 the last
+    base of a predecessor of v, or the empty walk at the start."""
+    if W >= C.shape[1]:
+        return 1 << 30
+    if off >= 1:
+        return int(C[i, W, pos[(v, off)]])
+    cands = [pos[(u, len(labels[u]))] for u, b in edges if b == v]
+    if v == v_s and j0 == 0:
+        cands.append(C.shape[2] - 1)
+    return min((int(C[i, W, p]) for p in cands), default=1 << 30)
+
+
+def gwf_walk_lengths(labels, edges, q: bytes, v_s: int, a_diff: int = 0, j0: int = 0, variant: str = ""):
+    """Algorithms 1-4 (extension form) with the walk length W~ of each
+    diagonal, written with one dictionary per score and explicit crossing
+    layers.  Returns (distance, end (v, j), entries) with entries the
+    sorted (score, v, k, offset, W~) of every extended wavefront.
+
+    `variant` swaps one rule for a plausible alternative, to show that the
+    inputs exercise each rule: "min_w" (the smaller W~ on offset ties and
+    within a round), "first_w" (the first crossing of a round into a
+    diagonal sets its W~), "lifo" (crossings followed depth first, no
+    rounds: the first path to reach a diagonal sets its W~), "ins_w" (an
+    insertion advances W~)."""
+    q = q.upper()
+    labs = [l.upper() for l in labels]
+    succ = {}
+    for a, b in edges:
+        succ.setdefault(a, []).append(b)
+    n = len(q)
+    better = (lambda x, y: x < y) if variant == "min_w" else (lambda x, y: x > y)
+    rec = {(v_s, -j0): j0}                # diagonal -> furthest offset (kept for the query's life)
+    wave = {(v_s, -j0): (j0, 0)}          # this score's diagonals before extension: (offset, W~)
+    entries = []
+    s = 0
+    while True:
+        ext = {}
+
+        def extend(v, k, o, W):
+            lab = labs[v]
+            while k + o < n and o < len(lab) and q[k + o] == ord(lab[o]):
+                o += 1
+                W += 1
+            ext[(v, k)] = (o, W)
+            rec[(v, k)] = o
+            return o, W
+
+        if variant == "lifo":
+            stack = list(wave.items())[::-1]
+            while stack:
+                (v, k), (o, W) = stack.pop()
+                o, W = extend(v, k, o, W)
+                if o == len(labs[v]):
+                    for u in reversed(succ.get(v, [])):
+                        t = (u, k + len(labs[v]))
+                        if t not in rec:
+                            rec[t] = 0
+                            stack.append((t, (0, W)))
+        layer = {} if variant == "lifo" else wave
+        while layer:
+            for (v, k), (o, W) in layer.items():
+                extend(v, k, o, W)
+            nxt = {}
+            for (v, k) in layer:
+                o, W = ext[(v, k)]
+                if o != len(labs[v]):
+                    continue
+                for u in succ.get(v, []):
+                    t = (u, k + len(labs[v]))
+                    if t in rec:
+                        continue
+                    if t not in nxt or (variant != "first_w" and better(W, nxt[t])):
+                        nxt[t] = W
+            for t in nxt:
+                rec[t] = 0
+            layer = {t: (0, W) for t, W in nxt.items()}
+        entries += [(s, v, k, o, W) for (v, k), (o, W) in ext.items()]
+        ends = [(v, o) for (v, k), (o, W) in ext.items()
+                if k + o == n and (o > 0 or (v == v_s and j0 == 0))]
+        if ends:
+            return s, min(ends), sorted(entries)
+        keep = ext
+        if a_diff > 0:
+            amax = max([0] + [k + o + W for (v, k), (o, W) in ext.items()])
+            if amax > a_diff:
+                keep = {d: x for d, x in ext.items() if amax - (d[1] + x[0] + x[1]) < a_diff}
+        cand = {}
+        for (v, k), (o, W) in keep.items():
+            L = len(labs[v])
+            c = []
+            if k + o < n:
+                c.append(((v, k + 1), o, W + (1 if variant == "ins_w" else 0)))
+            if o < L:
+                c.append(((v, k - 1), o + 1, W + 1))
+            if k + o < n and o < L:
+                c.append(((v, k), o + 1, W + 1))
+            for d, no, nw in c:
+                if rec.get(d, -1) >= no:
+                    continue
+                if d not in cand or no > cand[d][0] or (no == cand[d][0] and better(nw, cand[d][1])):
+                    cand[d] = (no, nw)
+        for d, (no, nw) in cand.items():
+            rec[d] = no
+        wave = cand
+        s += 1

@@ -13,7 +13,12 @@ mathematics fix (no GPU needed).
 * the value-capped form equals the dense form;
 * Algorithms 1-3 reach the Eq. 1 optimum and end; Algorithm 4 with a huge
   a_diff is exact and never beats the optimum otherwise; the work count
-  respects the diagonal-length bound of Section 2.4.
+  respects the diagonal-length bound of Section 2.4;
+* Algorithm 4 equals a pairwise wavefront with the same keep rule where every
+  walk has the same length up to each base; elsewhere every walk length W~ is
+  that of a walk aligning the consumed query at no more than the entry's
+  score, and the tie rules between walks of different lengths agree with an
+  independent implementation of them.
 """
 import numpy as np
 import pytest
@@ -771,3 +776,83 @@ def test_capped_equals_dense_medium_graphs():
             assert O.dp_capped((labels, edges), q, vs, d - 1)[0] == -1
         big += d >= 100
     assert big >= 30
+
+
+# ---------------------------------------------------------------------------
+# W~ where walks differ in length (indels, loops): soundness against Eq. 1
+# with the walk length as an extra index, and the tie rules of the reading
+# of W~ against an independent implementation of it.
+# ---------------------------------------------------------------------------
+def test_walk_length_is_a_real_walk_at_the_entry_score():
+    """Every extended entry (s, v, k, off, W~) of orc_gwf has a walk of
+    exactly W~ bases from the start to its front cell that aligns q[1..i]
+    at cost <= s (the chain of expansions, extensions and crossings that
+    made the entry costs exactly s); exact and pruned, with and without a
+    start offset, on tiny random graphs with cycles and self-loops.  An
+    insertion that advanced W~ (a planted slip, in the independent
+    implementation below) fails this."""
+    rng = np.random.default_rng(4301)
+    n_checked = n_slip = 0
+    for _ in range(200):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(2, 7)), max_label=5,
+                                                p_edge=float(rng.uniform(0.15, 0.5)), qlen=int(rng.integers(0, 25)))
+        j0 = int(rng.integers(0, len(labels[vs]) + 1)) if rng.random() < 0.3 else 0
+        C = pos = None
+        for a_diff in (0, 3, 8):
+            got = O.gwf((labels, edges), q, vs, a_diff=a_diff, j0=j0, entries_cap=1 << 16)
+            ent = got["entries"]
+            assert len(ent) == got["work"]
+            w_need = int(ent[:, 4].max()) + 1
+            if C is None or C.shape[1] < w_need + 1:
+                C, pos = refs.walk_length_costs(labels, edges, q, vs, w_need + 8, j0)
+            for s, v, k, o, W in ent.tolist():
+                assert refs.front_cell_cost(C, pos, labels, edges, vs, j0, k + o, v, o, W) <= s, \
+                    (labels, edges, q, vs, j0, a_diff, (s, v, k, o, W))
+                n_checked += 1
+            if j0 == 0:
+                _, _, slip = refs.gwf_walk_lengths(labels, edges, q, vs, a_diff, variant="ins_w")
+                if any(refs.front_cell_cost(C, pos, labels, edges, vs, 0, k + o, v, o, W) > s
+                       for s, v, k, o, W in slip):
+                    n_slip += 1
+    assert n_checked > 20000
+    assert n_slip > 100
+
+
+def test_walk_length_tie_rules_match_an_independent_implementation():
+    """orc_gwf's distance, end and every extended entry (score, v, k, off,
+    W~) equal those of an independent implementation of Algorithms 1-4 with
+    the same reading of W~ (the larger W~ on offset ties, crossings in rounds
+    with the larger W~ within a round and an earlier round first), exact and
+    at several a_diff, on tiny random graphs with cycles and self-loops and
+    on medium graphs with indel bubbles.  Each plausible alternative rule
+    (the smaller W~, the first crossing of a round, depth-first crossings
+    without rounds, an insertion advancing W~) disagrees with the oracle on
+    many of these runs, so the inputs exercise every rule."""
+    rng = np.random.default_rng(4302)
+    variants = ("min_w", "first_w", "lifo", "ins_w")
+    differs = dict.fromkeys(variants, 0)
+    runs = 0
+
+    def check(labels, edges, q, vs, a_diff, j0=0):
+        nonlocal runs
+        got = O.gwf((labels, edges), q, vs, a_diff=a_diff, j0=j0, entries_cap=1 << 22)
+        assert got["status"] == 0 and got["entries_total"] == len(got["entries"])
+        mine = (got["dist"], (got["end_v"], got["end_j"]), sorted(map(tuple, got["entries"].tolist())))
+        assert refs.gwf_walk_lengths(labels, edges, q, vs, a_diff, j0) == mine, (labels, edges, q, vs, a_diff, j0)
+        for var in variants:
+            differs[var] += refs.gwf_walk_lengths(labels, edges, q, vs, a_diff, j0, variant=var) != mine
+        runs += 1
+
+    for _ in range(300):
+        labels, edges, q, vs = refs.random_case(rng, n_vtx=int(rng.integers(2, 8)), max_label=5,
+                                                p_edge=float(rng.uniform(0.15, 0.5)), qlen=int(rng.integers(0, 30)))
+        j0 = int(rng.integers(0, len(labels[vs]) + 1)) if rng.random() < 0.3 else 0
+        for a_diff in (0, 2, 5, 12):
+            check(labels, edges, q, vs, a_diff, j0)
+    for _ in range(20):
+        labels, edges, q, vs, _ = refs.medium_case(rng)
+        q = q[:int(rng.integers(50, 800))]
+        for a_diff in (0, 10, 40):
+            check(labels, edges, q, vs, a_diff)
+    assert runs == 1260
+    assert min(differs.values()) > 100, differs
