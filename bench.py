@@ -318,6 +318,24 @@ def measure(args, workload, steps, warmup, prune, compare):
         except Exception as e:   # the comparison must not cost the benchmark line
             print(f"[bench] comparison legs failed: {e}", file=sys.stderr, flush=True)
             m["compare"] = {"error": str(e)}
+    if getattr(args, "end_to_end", False) and prune == 0:
+        try:
+            # the same batch from host memory through the host-buffer entry
+            # point (validation, query sort, copies in, alignment, results and
+            # walks back): a separate figure, never the line's value
+            ctx.config(**cfg)
+            cap = (bases // 4 + 64 * r.n) if o.traceback else 0
+            torch.cuda.synchronize()
+            th = time.perf_counter()
+            code, res_h, _, _ = gwfa.align_host(ctx, graph, r.seq, r.off, r.v_start, o, path_cap=cap)
+            e2e_s = time.perf_counter() - th
+            same = bool(code == 0 and (res_h["dist"] == res["dist"]).all())
+            m["end_to_end"] = {"entry": "gwfa_align_batch (host buffers, pageable)", "ms": e2e_s * 1000.0,
+                               "bases/s": bases / e2e_s, "code": int(code), "same_distances": same}
+            print(f"[bench] {workload} end to end from host buffers: {e2e_s:.2f} s", file=sys.stderr, flush=True)
+        except Exception as e:   # this figure must not cost the benchmark line
+            print(f"[bench] end-to-end leg failed: {e}", file=sys.stderr, flush=True)
+            m["end_to_end"] = {"error": str(e)}
     plan.close()
     graph.close()
     ctx.close()
@@ -342,6 +360,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the learned / heuristic pruning comparison after the timed steps")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-end-to-end", dest="end_to_end", action="store_false",
+                    help="skip the one call through the host-buffer entry point after the timed steps")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof FETCH/WRITE counters)")
     args = ap.parse_args()
