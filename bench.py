@@ -149,7 +149,7 @@ def compare_mode(ctx, graph, batch, out, n, bases, res_exact, stream, ev, o, par
                 min_excess=int(exc.min()) if len(exc) else 0, not_ok=int((~ok).sum()))
 
 
-def measure(args, workload, steps, warmup, prune, compare):
+def measure(args, workload, steps, warmup, prune, compare, end_to_end=False):
     """Times `steps` steps of the whole path on one workload (after `warmup`
     untimed ones) and returns the fields of the benchmark line."""
     import torch
@@ -318,7 +318,7 @@ def measure(args, workload, steps, warmup, prune, compare):
         except Exception as e:   # the comparison must not cost the benchmark line
             print(f"[bench] comparison legs failed: {e}", file=sys.stderr, flush=True)
             m["compare"] = {"error": str(e)}
-    if getattr(args, "end_to_end", False) and prune == 0:
+    if end_to_end and prune == 0:
         try:
             # the same batch from host memory through the host-buffer entry
             # point (validation, query sort, copies in, alignment, results and
@@ -373,7 +373,8 @@ def main():
         sys.exit(2)
 
     import torch
-    m, g, r = measure(args, args.workload, args.steps, args.warmup, args.prune, not args.no_compare)
+    m, g, r = measure(args, args.workload, args.steps, args.warmup, args.prune, not args.no_compare,
+                      args.end_to_end)
     line = {
         "metric": "query bases aligned/s on 1 GPU; exact vs learned-prune at <=1% reads over ED",
         "value": m["value"],
