@@ -379,7 +379,7 @@ __device__ __forceinline__ bool ends_walk(const Q& q, int32_t v, int32_t o, int3
 // of out-edges to cross (0 unless the vertex end was reached).
 template <class SH>
 __device__ __forceinline__ int record_entry(const Q& q, SH& S, int32_t v, int32_t k, int32_t o, int32_t W,
-                                            int32_t d, bool mark, int32_t Lv, int32_t deg) {
+                                            int32_t d, bool mark, int32_t Lv, int32_t deg, int2& lmax) {
     const int32_t i = k + o;
     // the record is written when the diagonal is new or may leave the
     // wavefront: at the vertex end, or with the query consumed (no mismatch
@@ -397,9 +397,11 @@ __device__ __forceinline__ int record_entry(const Q& q, SH& S, int32_t v, int32_
         if (q.ilo < q.qlen) atomicMax(&S.iend, i);
         else atomicMin(&S.endkey, ((ull)(uint32_t)v << 32) | (uint32_t)o);
     }
+    // Algorithm 4's a = i + W~ and the furthest row: this lane's maxima of the
+    // score, reduced over the wave and the workgroup once the score is extended
     if (q.track) {
-        atomicMax(&S.amax, i + W);
-        atomicMax(&S.imax, i);
+        lmax.x = max(lmax.x, i + W);
+        lmax.y = max(lmax.y, i);
     }
     return (o == Lv) ? deg : 0;
 }
@@ -408,13 +410,13 @@ __device__ __forceinline__ int record_entry(const Q& q, SH& S, int32_t v, int32_
 template <class SH>
 __device__ __forceinline__ int extend_entry(const KArgs& A, const Q& q, SH& S, int32_t v, int32_t k,
                                             int32_t& o, int32_t& W, int32_t d, bool mark, int64_t sb,
-                                            int32_t Lv, int32_t deg, uint32_t& chunks) {
+                                            int32_t Lv, int32_t deg, uint32_t& chunks, int2& lmax) {
     const int32_t i = k + o;
     const int32_t lim = min(q.qlen - i, Lv - o);
     const int32_t l = lcp(q.rd, q.q0 + i, ((q.q0 + q.qlen) >> 5) + 1, A.seg, sb + o, ((sb + Lv) >> 5) + 1, lim, chunks);
     o += l;
     W += l;
-    return record_entry(q, S, v, k, o, W, d, mark, Lv, deg);
+    return record_entry(q, S, v, k, o, W, d, mark, Lv, deg, lmax);
 }
 
 // Crossing candidate c: target u, diagonal k2 in u, walk length W, trace
@@ -705,6 +707,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             const int nb = 1 - cur;
             const Lists Ld = LL(nb);
             int32_t n1 = 0;           // diagonals produced by the expansion
+            int2 lmax = make_int2(0, 0);   // this lane's largest a = i + W~ and i of the score (tracked modes)
             ull tk = wall_clock64();
             if (s > 0) {
                 if (tid == 0) { S.found = 0; S.iend = -1; S.endkey = ~0ull; S.amax = 0; S.imax = 0; }
@@ -927,7 +930,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                             } else if (d < 0) {
                                 atomicOr(&S.flags, F_GROW);
                             } else {
-                                const int nc = record_entry(q, S, v, kj, o, Wj, d, nw, Lv, o == Lv ? vi.y : 0);
+                                const int nc = record_entry(q, S, v, kj, o, Wj, d, nw, Lv, o == Lv ? vi.y : 0, lmax);
                                 if (nc) { endm |= 1 << j; deg = nc; }
                                 Ld.e[p] = make_int4(v, kj, o, d);
                                 if ((p & (SAMP - 1)) == 0 && p < SAMP * nsamp(BLOCK)) S.samp[p / SAMP] = skey(v, kj);
@@ -996,7 +999,7 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
                         const bool push = q.tb && idx >= preset_hi;
                         const ull tprobe = __hip_atomic_load(&q.mkey[push ? (dhash(dkey(v, t)) & q.mask) : 0],
                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, vi.y, chunks);
+                        ncr = extend_entry(A, q, S, v, k, o, W, d, true, sb, Lv, vi.y, chunks, lmax);
                         if (idx >= preset_hi) t = push ? trace_push_from(q, S, v, t, tprobe) : -1;
                         Ld.e[idx].z = o;
                         if (q.track) Ld.w[idx] = W;
@@ -1095,6 +1098,16 @@ __device__ void align_read(const KArgs& A, char* __restrict__ arena, int r, Shar
             if (tid == 0) { const ull t2 = wall_clock64(); S.tick[1] += t2 - tk; tk = t2; }
             const int32_t ntot = xhi;
             work += ntot;
+            if (q.track) {   // one update of the score's maxima per wave
+                for (int m = 32; m >= 1; m >>= 1) {
+                    lmax.x = max(lmax.x, __shfl_xor(lmax.x, m, 64));
+                    lmax.y = max(lmax.y, __shfl_xor(lmax.y, m, 64));
+                }
+                if (__lane_id() == 0) {
+                    atomicMax(&S.amax, __builtin_amdgcn_readfirstlane(lmax.x));
+                    atomicMax(&S.imax, __builtin_amdgcn_readfirstlane(lmax.y));
+                }
+            }
             __syncthreads();
             const int found = __builtin_amdgcn_readfirstlane(S.found);
             const int32_t iend = q.ilo < q.qlen ? __builtin_amdgcn_readfirstlane(S.iend) : q.qlen;
