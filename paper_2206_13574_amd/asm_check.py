@@ -47,6 +47,11 @@ def _functions(text: str):
 
 
 def _blocks(lines):
+    """Basic blocks with their loop: the header of the innermost loop they
+    belong to, whether they are that header, and (for a header) the
+    enclosing loops.  The compiler writes a nested loop's header as a label
+    line naming the outermost parent, comment lines naming the other
+    parents, then "This Inner Loop Header"."""
     out, cur = [], None
     for line in lines:
         m = re.match(r"^(\.LBB\d+_\d+|; %bb\.\d+):(.*)$", line)
@@ -54,18 +59,27 @@ def _blocks(lines):
             if cur:
                 out.append(cur)
             lab = m.group(1).replace("; %bb.", "bb.")
-            cur = {"lab": lab, "loop": None, "parents": [], "text": [], "header": False}
+            cur = {"lab": lab, "loop": None, "parents": [], "text": [], "header": False, "code": False}
             note = m.group(2)
             mm = re.search(r"in Loop: Header=(BB\d+_\d+)", note)
             if mm:
                 cur["loop"] = mm.group(1)
+            mm = re.search(r"Parent Loop (BB\d+_\d+)", note)
+            if mm:
+                cur["parents"].append(mm.group(1))
             if "Loop Header" in note:
                 cur["header"] = True
                 cur["loop"] = lab.lstrip(".").replace("LBB", "BB")
         elif cur is not None:
-            mm = re.search(r"Parent Loop (BB\d+_\d+)", line)
-            if mm:
-                cur["parents"].append(mm.group(1))
+            if not cur["code"] and line.lstrip().startswith(";"):
+                mm = re.search(r"Parent Loop (BB\d+_\d+)", line)
+                if mm:
+                    cur["parents"].append(mm.group(1))
+                elif "Loop Header" in line:
+                    cur["header"] = True
+                    cur["loop"] = cur["lab"].lstrip(".").replace("LBB", "BB")
+            elif line.strip():
+                cur["code"] = True
             cur["text"].append(line)
     if cur:
         out.append(cur)
@@ -94,6 +108,29 @@ def flagged_loops(lines) -> list:
         lane_exit = any(_LOOP_EXIT.search(t) for b in own[h] for t in b["text"])
         if barrier and lane_exit:
             out.append(h)
+    return out
+
+
+def lane_loops(lines) -> list:
+    """Loops that step through the active lanes of a wave one at a time
+    (find the first lane of a mask, read that lane's value, clear the lane):
+    the form the compiler's atomic optimizer gives an atomic whose address is
+    the same in every lane and whose value is not, before one atomic from
+    one lane.  Returns [(header, nesting depth)], depth 1 for an outermost
+    loop.  Inside the per-entry loops such a loop costs several instructions
+    per active lane for every entry."""
+    own, depth = defaultdict(list), {}
+    for b in _blocks(lines):
+        if not b["loop"]:
+            continue
+        own[b["loop"]].append(b)
+        if b["header"]:
+            depth[b["loop"]] = len(b["parents"]) + 1
+    out = []
+    for h, bs in own.items():
+        text = [t for b in bs for t in b["text"]]
+        if any("s_ff1_i32_b64" in t for t in text) and any("v_readlane_b32" in t for t in text):
+            out.append((h, depth.get(h, 1)))
     return out
 
 
